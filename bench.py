@@ -1,0 +1,215 @@
+"""Benchmark: CG time-to-1e-8 residual, mixed vs FP64; Dslash GFLOP/s and fraction of peak HBM.
+
+Workload (the paper's single-GPU CG job shape, Sec. 3, Fig. 1 / Table 2): a 20^3x64 lattice with
+near-identity SU(3) links exp(i 0.3 H) standing in for the HYP-smeared MILC asqtad coarse ensemble,
+m = 0.01, one Gaussian even-site source. One step = one mixed-precision solve (FP32 iterations, FP64
+reliable updates) of (m^2 - D_eo D_oe) x = b from x = 0 to an FP64 true relative residual of 1e-8, with
+links packed and source resident in HBM before the timed region. Beside it, in the same run:
+  * the plain FP64 GPU CG to the same residual (the comparator),
+  * the half-Dslash kernel timed with HIP events on the stream it runs on (roofline),
+  * the FP64 CPU oracle timed on a bounded sample (FP64 CG iterations on the same lattice).
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "CG time-to-1e-8 residual, mixed vs FP64; Dslash GFLOP/s + % peak HBM"
+HBM_PEAK_GBS = 8000.0
+FLOP_PER_SITE = 570  # one half-Dslash output site: 8 SU(3) mat-vecs (66) + 7 colour-vector adds (6)
+# algorithmic bytes per output site of one half-Dslash: 8 links + 1 input vector (perfect neighbour
+# reuse) + 1 output vector
+LINK_BYTES = {("f64", 18): 144, ("f32", 18): 72, ("f32", 12): 48, ("f16", 18): 36, ("f16", 12): 24,
+              ("bf16", 18): 36, ("bf16", 12): 24}
+VEC_BYTES = {"f64": 48, "f32": 24, "f16": 16, "bf16": 12}
+
+
+def dslash_bytes_per_site(prec, recon):
+    return 8 * LINK_BYTES[(prec, recon)] + 2 * VEC_BYTES[prec]
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor()
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--inner", default="f32", choices=["f32", "f16", "bf16"])
+    ap.add_argument("--recon", type=int, default=18, choices=[18, 12])
+    ap.add_argument("--dims", type=int, nargs=4, default=[20, 20, 20, 64])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparator solves")
+    ap.add_argument("--dslash-reps", type=int, default=200)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the solver has no multi-GPU path",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import lattice_inputs as li
+    import paper_1511_00088_amd as sp
+
+    def log(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    dev = "cuda:0"
+    dims = tuple(args.dims)
+    log(f"generating 20^3x64-style inputs dims={dims}")
+    c = li.cfg1(dims)
+    mass, tol = c["mass"], c["tol"]
+    lat = sp.Lattice(dims)
+    links = torch.from_numpy(c["links"]).to(dev)
+    b = torch.from_numpy(c["source"]).to(dev)
+    G = sp.Gauge(lat, links, lo_prec=args.inner, recon=args.recon)
+    G64 = sp.Gauge(lat, links, lo_prec="f64")
+    del links
+    log("tuning the half-Dslash launch")
+    sp.tune_dslash(G, args.inner)
+    sp.tune_dslash(G64, "f64")
+    ws = sp.Workspace()
+    stream = torch.cuda.current_stream()
+
+    def solve_mixed():
+        return sp.cg_solve(G, mass, b, tol=tol, inner=args.inner, workspace=ws)
+
+    def solve_fp64(t=tol):
+        return sp.cg_solve(G64, mass, b, tol=t, inner="f64", workspace=ws)
+
+    log(f"warmup {args.warmup}")
+    for _ in range(args.warmup):
+        x, st = solve_mixed()
+    torch.cuda.synchronize()
+    log(f"timing {args.steps} mixed-precision solves")
+    t0 = time.perf_counter()
+    per = []
+    for _ in range(args.steps):
+        x, st = solve_mixed()
+        per.append(st.seconds)
+    torch.cuda.synchronize()
+    t_mixed = (time.perf_counter() - t0) / max(args.steps, 1)
+    assert st.converged, f"mixed solve did not converge: {st}"
+    log(f"mixed: {t_mixed * 1e3:.2f} ms/solve iters={st.iters} ru={st.reliable_updates} "
+        f"resid={st.true_rel_resid:.3e}")
+
+    extra = {}
+    if not args.no_fp64:
+        x64, st64 = solve_fp64()
+        torch.cuda.synchronize()
+        n64 = max(1, args.steps // 2)
+        t0 = time.perf_counter()
+        for _ in range(n64):
+            x64, st64 = solve_fp64()
+        torch.cuda.synchronize()
+        t_fp64 = (time.perf_counter() - t0) / n64
+        xref, stref = solve_fp64(1e-12)
+        err = float(torch.linalg.norm(x - xref) / torch.linalg.norm(xref))
+        err64 = float(torch.linalg.norm(x64 - xref) / torch.linalg.norm(xref))
+        log(f"fp64: {t_fp64 * 1e3:.2f} ms/solve iters={st64.iters}; mixed err vs 1e-12 FP64 solve {err:.3e}")
+        extra.update(fp64_cg_s=t_fp64, fp64_iters=st64.iters, speedup_vs_fp64=t_fp64 / t_mixed,
+                     err_mixed_vs_fp64_1e12=err, err_fp64_vs_fp64_1e12=err64, ref_iters_1e12=stref.iters,
+                     fp64_true_rel_resid=st64.true_rel_resid)
+
+    # --- dominant kernel: half-Dslash in the inner precision, HIP events on the launch stream ---
+    inp = sp.pack_vec(lat, b, args.inner)
+    out = torch.empty_like(inp)
+    for _ in range(20):
+        sp.dslash_packed(G, args.inner, inp, 1, out)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.dslash_reps):
+        sp.dslash_packed(G, args.inner, inp, 1, out)
+    e1.record(stream)
+    e1.synchronize()
+    t_d = e0.elapsed_time(e1) / 1e3 / args.dslash_reps
+    bps = dslash_bytes_per_site(args.inner, args.recon)
+    achieved = bps * lat.Vh / t_d / 1e9
+    gflops = FLOP_PER_SITE * lat.Vh / t_d / 1e9
+    # FP64 half-Dslash as well (the reliable-update and plain-FP64 kernel)
+    inp64 = sp.pack_vec(lat, b, "f64")
+    out64 = torch.empty_like(inp64)
+    for _ in range(10):
+        sp.dslash_packed(G64, "f64", inp64, 1, out64)
+    e0.record(stream)
+    for _ in range(args.dslash_reps // 2):
+        sp.dslash_packed(G64, "f64", inp64, 1, out64)
+    e1.record(stream)
+    e1.synchronize()
+    t_d64 = e0.elapsed_time(e1) / 1e3 / (args.dslash_reps // 2)
+    log(f"dslash {args.inner} r{args.recon}: {t_d * 1e6:.2f} us, {achieved:.0f} GB/s, {gflops:.0f} GFLOP/s; "
+        f"f64: {t_d64 * 1e6:.2f} us")
+
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+
+        oracle.build(force=False)
+        n_it = 40
+        log(f"CPU oracle: {n_it} FP64 CG iterations on {dims}")
+        bh = c["source"]
+        t0 = time.perf_counter()
+        _, status, it, _ = oracle.cg_solve(dims, c["links"], mass, bh, tol=1e-30, max_iter=n_it)
+        t_cpu = time.perf_counter() - t0
+        iters_needed = extra.get("fp64_iters", st.iters)
+        per_iter = t_cpu / (n_it + 2)  # n_it iterations + initial and final residual applications
+        cpu = {"value": per_iter * iters_needed, "unit": "s", "cores": 1, "kind": "oracle",
+               "sample": f"{n_it} FP64 CG iterations of the single-threaded oracle on {dims[0]}^3x{dims[3]} "
+                         f"({t_cpu:.1f} s), scaled to the {iters_needed} iterations FP64 CG needs for 1e-8; "
+                         f"host {cpu_model()}, {os.cpu_count()} logical CPUs"}
+        log(f"CPU oracle: {per_iter * 1e3:.1f} ms/iteration -> {cpu['value']:.1f} s")
+
+    line = {
+        "metric": METRIC,
+        "value": t_mixed,
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t_mixed * 1e3,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.inner,
+        "data": "synthetic",
+        "config": {"workload": f"even-odd mixed-precision staggered CG, {dims[0]}^3x{dims[3]}, near-identity "
+                               f"SU(3) links eps=0.3, m={mass}, Gaussian source, tol={tol}",
+                   "dims": list(dims), "mass": mass, "tol": tol, "inner": args.inner, "recon": args.recon,
+                   "reliable_update": "FP64 true residual every 100 iterations or on |r| < 0.1 |r_ru|",
+                   "parallelism": "single GPU"},
+        "iters": st.iters,
+        "reliable_updates": st.reliable_updates,
+        "true_rel_resid": st.true_rel_resid,
+        "solve_s_min": min(per) if per else None,
+        "dslash": {"prec": args.inner, "recon": args.recon, "us": t_d * 1e6, "gflops": gflops,
+                   "bytes_per_site": bps, "hbm_frac": achieved / HBM_PEAK_GBS, "f64_us": t_d64 * 1e6,
+                   "f64_gflops": FLOP_PER_SITE * lat.Vh / t_d64 / 1e9},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+        "cpu_baseline": cpu,
+    }
+    line.update(extra)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

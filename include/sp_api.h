@@ -1,0 +1,199 @@
+/* sp_api.h -- C-ABI of libstagcg.so, the MI355X (gfx950) even-odd staggered CG library.
+ *
+ * What it computes. The paper (Sec. 3, "CG Performance"; Fig. 1, Table 2) measures a mixed-precision
+ * conjugate-gradient inverter for HYP-smeared staggered quarks on 20^3x64 lattices, in which single
+ * precision dominates and a small double-precision part keeps the answer exact. The operator is the
+ * standard staggered one (the paper does not print it):
+ *   (D chi)(n) = 1/2 sum_mu eta_mu(n) [ U_mu(n) chi(n+mu) - U_mu(n-mu)^dag chi(n-mu) ],
+ *   eta_0 = 1, eta_1 = (-1)^x, eta_2 = (-1)^(x+y), eta_3 = (-1)^(x+y+z),
+ * and the solver works on even sites with A = m^2 - D_eo D_oe (Hermitian positive definite).
+ *
+ * Conventions shared by every entry point.
+ *  - Natural layout (what callers hand in and get back): complex128 interleaved (re, im);
+ *      links U[mu][lex][i][j], mu = 0..3 = x,y,z,t, lex = x + X*(y + Y*(z + Z*t));
+ *      half vectors v[cb][c] with cb = lex >> 1 over sites of one parity (even = (x+y+z+t) even).
+ *  - Packed layout (what the kernels read): produced only by sp_gauge_pack / sp_vec_pack, opaque to the
+ *    caller apart from its size (sp_gauge_bytes / sp_vec_bytes); it is structure-of-arrays per parity
+ *    and direction so that neighbouring lattice sites sit in neighbouring 16-byte words.
+ *  - Pointers are DEVICE pointers unless a comment says host. All buffers belong to the caller; the
+ *    library never frees them and keeps no reference after a call returns. Device buffers must be
+ *    256-byte aligned (hipMalloc / torch allocations are).
+ *  - `stream` is a hipStream_t (0 = the null stream). sp_gauge_pack, sp_vec_pack, sp_vec_unpack and
+ *    sp_dslash only enqueue work on it and return. sp_cg_solve, sp_cg_solve_batched and sp_cg_force
+ *    enqueue on it and return once it has reached their end (they need convergence decisions and
+ *    statistics on the host).
+ *  - Errors: the return value is an sp_status. Negative codes leave outputs unspecified;
+ *    SP_NOT_CONVERGED (positive) leaves the best solution and valid statistics. sp_strerror() names a
+ *    code, sp_last_error() gives the detailed message of the calling thread's last failure (including
+ *    the HIP error string for SP_ERR_HIP). No C++ exception crosses this interface.
+ *  - Not reentrant on one workspace: two calls that share a workspace must not overlap.
+ */
+#ifndef SP_API_H
+#define SP_API_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Storage precisions. Arithmetic is FP64 for SP_F64 and FP32 for the other three. */
+typedef enum { SP_F64 = 0, SP_F32 = 1, SP_F16 = 2, SP_BF16 = 3 } sp_prec;
+
+typedef enum {
+    SP_OK = 0,
+    SP_NOT_CONVERGED = 1,     /* max_iter reached or residual stagnated; outputs valid */
+    SP_ERR_INVALID_ARG = -1,  /* null pointer, bad enum, bad parity, bad tolerance ... */
+    SP_ERR_ODD_EXTENT = -2,   /* a lattice extent is odd or < 2 */
+    SP_ERR_UNSUPPORTED = -3,  /* combination not built (e.g. FP64 with recon 12, too large a lattice) */
+    SP_ERR_WORKSPACE = -4,    /* workspace null or smaller than the *_workspace_bytes query */
+    SP_ERR_HIP = -5,          /* a HIP runtime call failed */
+    SP_ERR_BREAKDOWN = -6     /* CG breakdown: Re<p,Ap> <= 0 or a non-finite scalar (e.g. NaN source) */
+} sp_status;
+
+/* Lattice geometry: extents X, Y, Z, T (each even, >= 2; V/2 < 2^24) and the time boundary
+ * (0 periodic, 1 antiperiodic: the t-links on the last time slice enter with a factor -1). */
+typedef struct {
+    int32_t dims[4];
+    int32_t bc_t;
+} sp_geom;
+
+/* A packed gauge field. f64: FP64 recon-18 packing (needed by every solve: true residuals);
+ * lo: the packing of the inner precision lo_prec with recon 18 (all 9 complex entries) or 12 (first two
+ * rows; the third is rebuilt as conj(row0 x row1), exact for SU(3) links). lo may equal f64 when
+ * lo_prec is SP_F64. */
+typedef struct {
+    const void* f64;
+    const void* lo;
+    int32_t lo_prec;
+    int32_t recon;
+} sp_gauge;
+
+/* Solver parameters.
+ *  tol        stop when the FP64 true residual |b - A x| / |b| <= tol (> 0)
+ *  max_iter   iteration cap (> 0)
+ *  inner      precision of the iterated vectors and links: SP_F64 gives plain FP64 CG; SP_F32, SP_F16,
+ *             SP_BF16 give mixed precision with FP64 reliable updates
+ *  delta      extra reliable update when |r_iterated| < delta * |r at the last update| (0 disables)
+ *  ru_every   reliable update at least every ru_every iterations (ignored for SP_F64; <= 0 picks 100
+ *             for SP_F32 and 50 for 16-bit storage)
+ *  poll_chunk iterations per device-side chunk between host convergence polls (<= 0 picks 50)
+ *  use_x0     1: x_e holds the initial guess on entry; 0: start from zero
+ *  use_graph  1: capture each chunk in a hipGraph and replay it; 0: launch kernels one by one */
+typedef struct {
+    double tol;
+    int32_t max_iter;
+    int32_t inner;
+    double delta;
+    int32_t ru_every;
+    int32_t poll_chunk;
+    int32_t use_x0;
+    int32_t use_graph;
+} sp_cg_params;
+
+/* Host-side statistics of one solve. */
+typedef struct {
+    int32_t iters;             /* CG iterations performed */
+    int32_t reliable_updates;  /* FP64 true-residual recomputations after the initial one */
+    int32_t converged;         /* 1 if true_rel_resid <= tol */
+    int32_t status;            /* sp_status of this system */
+    double true_rel_resid;     /* FP64 |b - A x| / |b| at the last reliable update */
+    double seconds;            /* wall time of the solve, packing of b and x included */
+} sp_cg_stats;
+
+/* One system of a batch. Systems that share (U, geometry) are solved with one multi-right-hand-side
+ * operator application per iteration (each link is loaded once for all of them). */
+typedef struct {
+    const sp_geom* g;
+    const sp_gauge* U;
+    double mass;
+    const double* b_e;  /* device, natural [V/2][3] complex128 */
+    double* x_e;        /* device, natural [V/2][3] complex128; in: initial guess if use_x0 */
+} sp_system;
+
+/* Library version (major * 10000 + minor * 100 + patch). */
+int sp_version(void);
+
+/* Static text for an sp_status code. */
+const char* sp_strerror(int code);
+
+/* Detailed message of the calling thread's last failing call ("" if none). */
+const char* sp_last_error(void);
+
+/* Bytes of a packed gauge field (all 4 directions, both parities) for prec and recon (18 or 12). */
+size_t sp_gauge_bytes(const sp_geom* g, int prec, int recon);
+
+/* Pack natural links (device, complex128 [4][V][3][3]) into out (device, sp_gauge_bytes). Rounds to
+ * nearest-even when narrowing. Asynchronous on stream. */
+int sp_gauge_pack(const sp_geom* g, const double* links_nat, int prec, int recon, void* out, void* stream);
+
+/* Bytes of one packed parity-half vector of precision prec (FP16 includes a per-site FP32 norm). */
+size_t sp_vec_bytes(const sp_geom* g, int prec);
+
+/* Pack a natural half vector (device, complex128 [V/2][3]) into out (sp_vec_bytes). Asynchronous. */
+int sp_vec_pack(const sp_geom* g, const double* v_nat, int prec, void* out, void* stream);
+
+/* Unpack a packed half vector into natural complex128 [V/2][3]. Asynchronous. */
+int sp_vec_unpack(const sp_geom* g, const void* v, int prec, double* v_nat, void* stream);
+
+/* Half staggered operator: out (parity out_parity) = D_{out_parity, 1-out_parity} in, both packed with
+ * precision prec. Links: U->f64 when prec is SP_F64, else U->lo (U->lo_prec must equal prec).
+ * Asynchronous on stream. This is the kernel the solver spends most of its time in. */
+int sp_dslash(const sp_geom* g, const sp_gauge* U, int prec, const void* in, void* out, int out_parity,
+              void* stream);
+
+/* Workspace bytes for sp_cg_solve (nsys = 1, systems[0] describes it; b_e/x_e may be null) or for
+ * sp_cg_solve_batched over the same system list. */
+size_t sp_cg_workspace_bytes(int nsys, const sp_system* systems, const sp_cg_params* params);
+
+/* Solve (m^2 - D_eo D_oe) x_e = b_e. b_e, x_e: device natural [V/2][3] complex128. stats: host,
+ * nullable. ws: device workspace of at least sp_cg_workspace_bytes bytes. Returns SP_OK,
+ * SP_NOT_CONVERGED or an error. Synchronous with respect to stream. */
+int sp_cg_solve(const sp_geom* g, const sp_gauge* U, double mass, const double* b_e, double* x_e,
+                const sp_cg_params* params, sp_cg_stats* stats, void* ws, size_t ws_bytes, void* stream);
+
+/* Solve nsys independent systems together: systems sharing a gauge field and geometry form groups of up
+ * to 8 right-hand sides; all groups advance in one launch per kernel, captured in a hipGraph per chunk
+ * of iterations; converged systems stop updating while the others continue. stats: host array of nsys
+ * (nullable). Returns SP_OK if every system converged, SP_NOT_CONVERGED if any did not, or an error.
+ * Synchronous with respect to stream. */
+int sp_cg_solve_batched(int nsys, const sp_system* systems, const sp_cg_params* params,
+                        sp_cg_stats* stats, void* ws, size_t ws_bytes, void* stream);
+
+/* Workspace bytes for sp_cg_force on geometry g. */
+size_t sp_force_workspace_bytes(const sp_geom* g);
+
+/* Adjoint link and mass gradient of a real loss l(x) with x = A^-1 b, given x_e and
+ * lambda_e = A^-1 (dl/dx) (device natural [V/2][3] complex128), U->f64 packed links:
+ *   gamma[4][V][3][3] (device, complex128, overwritten) = dl/dU_mu(n) with the complex convention
+ *     dl/dRe U + i dl/dIm U:
+ *       n even:  1/2 eta_mu(n) s [ lambda(n) y_x(n+mu)^dag + x(n) y_l(n+mu)^dag ],
+ *       n odd:  -1/2 eta_mu(n) s [ y_x(n) lambda(n+mu)^dag + y_l(n) x(n+mu)^dag ],
+ *     y_x = D_oe x, y_l = D_oe lambda, s the boundary sign of the link;
+ *   force[4][V][3][3] (nullable) = TA(U gamma^dag), TA(W) = (W - W^dag)/2 - tr(W - W^dag)/6, the
+ *     su(3)-projected force: for U -> exp(i t T) U, dl/dt = i tr(force T);
+ *   grad_mass (device double, nullable) = -2 m Re<lambda, x>.
+ * The gradient with respect to b is lambda itself. Synchronous with respect to stream. */
+int sp_cg_force(const sp_geom* g, const sp_gauge* U, double mass, const double* x_e,
+                const double* lambda_e, double* gamma, double* force, double* grad_mass, void* ws,
+                size_t ws_bytes, void* stream);
+
+/* Autotune the half-operator launch (block size, XCD-aware block order) for (g, prec, U->recon) by
+ * timing it with HIP events on stream; in and out are scratch packed vectors of that precision. The
+ * choice is kept for the process and used by sp_dslash and the solvers. best_ms (host, nullable)
+ * receives the best time per launch. */
+int sp_tune_dslash(const sp_geom* g, const sp_gauge* U, int prec, void* in, void* out, void* stream,
+                   double* best_ms);
+
+/* Save / load the tuned launches as JSON text (path on the host file system). Load merges entries. */
+int sp_tune_save(const char* path);
+int sp_tune_load(const char* path);
+
+/* Drop cached hipGraphs and tuning entries. */
+void sp_release_cache(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SP_API_H */

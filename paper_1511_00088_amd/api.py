@@ -1,0 +1,248 @@
+"""Torch-facing wrappers of libstagcg.so.
+
+PyTorch provides device memory and streams only: every step of the operator, the solver and the
+gradient runs in the library's HIP kernels. Tensors are complex128 in the natural layout of the C-ABI
+(links [4][V][3][3], even-site vectors [V/2][3]) and must live on the current HIP device.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib as L
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t: torch.Tensor):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _prec(p) -> int:
+    if isinstance(p, str):
+        return L.PREC[p]
+    return int(p)
+
+
+def _check_c128(t: torch.Tensor, shape, name):
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.complex128 or not t.is_cuda:
+        raise TypeError(f"{name} must be a complex128 GPU tensor")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+class Lattice:
+    """Lattice extents (X, Y, Z, T), each even, and the time boundary (0 periodic, 1 antiperiodic)."""
+
+    def __init__(self, dims, bc_t: int = 0):
+        self.dims = tuple(int(d) for d in dims)
+        if len(self.dims) != 4:
+            raise ValueError("dims must have 4 entries")
+        self.bc_t = int(bc_t)
+        self.V = self.dims[0] * self.dims[1] * self.dims[2] * self.dims[3]
+        self.Vh = self.V // 2
+        self.geom = L.sp_geom((ctypes.c_int32 * 4)(*self.dims), self.bc_t)
+
+    def vec_bytes(self, prec) -> int:
+        return int(L.load().sp_vec_bytes(ctypes.byref(self.geom), _prec(prec)))
+
+    def gauge_bytes(self, prec, recon=18) -> int:
+        return int(L.load().sp_gauge_bytes(ctypes.byref(self.geom), _prec(prec), int(recon)))
+
+
+def pack_gauge(lat: Lattice, links: torch.Tensor, prec, recon: int = 18) -> torch.Tensor:
+    _check_c128(links, (4, lat.V, 3, 3), "links")
+    nbytes = lat.gauge_bytes(prec, recon)
+    if nbytes == 0:
+        raise ValueError(f"unsupported packing prec={prec} recon={recon}")
+    out = torch.empty(nbytes, dtype=torch.uint8, device=links.device)
+    L.check(L.load().sp_gauge_pack(ctypes.byref(lat.geom), _ptr(links), _prec(prec), int(recon), _ptr(out),
+                                   _stream()), "sp_gauge_pack")
+    return out
+
+
+class Gauge:
+    """A gauge field packed for the GPU: FP64 (recon 18) plus an optional low-precision packing."""
+
+    def __init__(self, lat: Lattice, links: torch.Tensor, lo_prec="f32", recon: int = 18):
+        self.lat = lat
+        self.f64 = pack_gauge(lat, links, "f64", 18)
+        self.lo_prec = _prec(lo_prec)
+        self.recon = int(recon) if self.lo_prec != L.SP_F64 else 18
+        self.lo = self.f64 if self.lo_prec == L.SP_F64 else pack_gauge(lat, links, self.lo_prec, self.recon)
+        self.struct = L.sp_gauge(self.f64.data_ptr(), self.lo.data_ptr(), self.lo_prec, self.recon)
+
+
+def pack_vec(lat: Lattice, v: torch.Tensor, prec) -> torch.Tensor:
+    _check_c128(v, (lat.Vh, 3), "vector")
+    out = torch.empty(lat.vec_bytes(prec), dtype=torch.uint8, device=v.device)
+    L.check(L.load().sp_vec_pack(ctypes.byref(lat.geom), _ptr(v), _prec(prec), _ptr(out), _stream()),
+            "sp_vec_pack")
+    return out
+
+
+def unpack_vec(lat: Lattice, packed: torch.Tensor, prec) -> torch.Tensor:
+    out = torch.empty((lat.Vh, 3), dtype=torch.complex128, device=packed.device)
+    L.check(L.load().sp_vec_unpack(ctypes.byref(lat.geom), _ptr(packed), _prec(prec), _ptr(out), _stream()),
+            "sp_vec_unpack")
+    return out
+
+
+def dslash_packed(gauge: Gauge, prec, inp: torch.Tensor, out_parity: int, out: torch.Tensor | None = None):
+    """out (parity out_parity) = D_{p,1-p} inp on packed vectors of precision prec."""
+    lat = gauge.lat
+    if out is None:
+        out = torch.empty(lat.vec_bytes(prec), dtype=torch.uint8, device=inp.device)
+    L.check(L.load().sp_dslash(ctypes.byref(lat.geom), ctypes.byref(gauge.struct), _prec(prec), _ptr(inp),
+                               _ptr(out), int(out_parity), _stream()), "sp_dslash")
+    return out
+
+
+def dslash(gauge: Gauge, v: torch.Tensor, out_parity: int, prec="f64") -> torch.Tensor:
+    """Half operator on a natural complex128 vector: pack to prec, apply, unpack."""
+    lat = gauge.lat
+    return unpack_vec(lat, dslash_packed(gauge, prec, pack_vec(lat, v, prec), out_parity), prec)
+
+
+@dataclass
+class SolveStats:
+    iters: int
+    reliable_updates: int
+    converged: bool
+    status: int
+    true_rel_resid: float
+    seconds: float
+
+
+def _params(tol, max_iter, inner, delta, ru_every, poll_chunk, use_x0, use_graph):
+    return L.sp_cg_params(float(tol), int(max_iter), _prec(inner), float(delta), int(ru_every), int(poll_chunk),
+                          int(use_x0), int(use_graph))
+
+
+def _stats(s: L.sp_cg_stats) -> SolveStats:
+    return SolveStats(int(s.iters), int(s.reliable_updates), bool(s.converged), int(s.status),
+                      float(s.true_rel_resid), float(s.seconds))
+
+
+class Workspace:
+    """A reusable device workspace (grown on demand)."""
+
+    def __init__(self):
+        self.buf = None
+
+    def get(self, nbytes: int, device) -> torch.Tensor:
+        if self.buf is None or self.buf.numel() < nbytes or self.buf.device != torch.device(device):
+            self.buf = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+        return self.buf
+
+
+_default_ws = Workspace()
+
+
+def cg_solve(gauge: Gauge, mass: float, b: torch.Tensor, tol: float = 1e-8, inner="f32", max_iter: int = 100000,
+             delta: float = 0.1, ru_every: int = 0, poll_chunk: int = 50, x0: torch.Tensor | None = None,
+             use_graph: bool = True, workspace: Workspace | None = None, out: torch.Tensor | None = None,
+             raise_on_not_converged: bool = False):
+    """Solve (m^2 - D_eo D_oe) x = b on even sites. Returns (x, SolveStats)."""
+    lat = gauge.lat
+    _check_c128(b, (lat.Vh, 3), "b")
+    inner_p = _prec(inner)
+    if inner_p != L.SP_F64 and inner_p != gauge.lo_prec:
+        raise ValueError("the gauge field's low-precision packing must match the inner precision")
+    x = out if out is not None else torch.empty_like(b)
+    if x0 is not None:
+        _check_c128(x0, (lat.Vh, 3), "x0")
+        x.copy_(x0)
+    prm = _params(tol, max_iter, inner_p, delta, ru_every, poll_chunk, x0 is not None, use_graph)
+    sysd = L.sp_system(ctypes.pointer(lat.geom), ctypes.pointer(gauge.struct), float(mass), b.data_ptr(),
+                       x.data_ptr())
+    lib = L.load()
+    nbytes = lib.sp_cg_workspace_bytes(1, ctypes.byref(sysd), ctypes.byref(prm))
+    if nbytes == 0:
+        raise L.StagError(L.SP_ERR_INVALID_ARG, "sp_cg_workspace_bytes")
+    ws = (workspace or _default_ws).get(nbytes, b.device)
+    st = L.sp_cg_stats()
+    rc = lib.sp_cg_solve(ctypes.byref(lat.geom), ctypes.byref(gauge.struct), float(mass), _ptr(b), _ptr(x),
+                         ctypes.byref(prm), ctypes.byref(st), _ptr(ws), ctypes.c_size_t(ws.numel()), _stream())
+    L.check(rc, "sp_cg_solve", allow_not_converged=not raise_on_not_converged)
+    return x, _stats(st)
+
+
+def cg_solve_batched(systems, tol: float = 1e-8, inner="f32", max_iter: int = 100000, delta: float = 0.1,
+                     ru_every: int = 0, poll_chunk: int = 50, use_graph: bool = True,
+                     workspace: Workspace | None = None):
+    """Solve many systems together. systems: list of (Gauge, mass, b). Returns (list of x, list of stats)."""
+    n = len(systems)
+    if n == 0:
+        return [], []
+    inner_p = _prec(inner)
+    arr = (L.sp_system * n)()
+    xs = []
+    for i, (gauge, mass, b) in enumerate(systems):
+        _check_c128(b, (gauge.lat.Vh, 3), f"b[{i}]")
+        if inner_p != L.SP_F64 and inner_p != gauge.lo_prec:
+            raise ValueError("every gauge field's low-precision packing must match the inner precision")
+        x = torch.empty_like(b)
+        xs.append(x)
+        arr[i] = L.sp_system(ctypes.pointer(gauge.lat.geom), ctypes.pointer(gauge.struct), float(mass),
+                             b.data_ptr(), x.data_ptr())
+    prm = _params(tol, max_iter, inner_p, delta, ru_every, poll_chunk, 0, use_graph)
+    lib = L.load()
+    nbytes = lib.sp_cg_workspace_bytes(n, arr, ctypes.byref(prm))
+    if nbytes == 0:
+        raise L.StagError(L.SP_ERR_INVALID_ARG, "sp_cg_workspace_bytes")
+    dev = systems[0][2].device
+    ws = (workspace or _default_ws).get(nbytes, dev)
+    st = (L.sp_cg_stats * n)()
+    rc = lib.sp_cg_solve_batched(n, arr, ctypes.byref(prm), st, _ptr(ws), ctypes.c_size_t(ws.numel()), _stream())
+    L.check(rc, "sp_cg_solve_batched", allow_not_converged=True)
+    return xs, [_stats(s) for s in st]
+
+
+def cg_force(gauge: Gauge, mass: float, x: torch.Tensor, lam: torch.Tensor, want_force: bool = True):
+    """Link gradient gamma = dl/dU, su(3) force TA(U gamma^dag) and dl/dm = -2 m Re<lam, x>."""
+    lat = gauge.lat
+    _check_c128(x, (lat.Vh, 3), "x")
+    _check_c128(lam, (lat.Vh, 3), "lambda")
+    dev = x.device
+    gamma = torch.empty((4, lat.V, 3, 3), dtype=torch.complex128, device=dev)
+    force = torch.empty_like(gamma) if want_force else None
+    dmass = torch.empty((), dtype=torch.float64, device=dev)
+    lib = L.load()
+    nbytes = lib.sp_force_workspace_bytes(ctypes.byref(lat.geom))
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    rc = lib.sp_cg_force(ctypes.byref(lat.geom), ctypes.byref(gauge.struct), float(mass), _ptr(x), _ptr(lam),
+                         _ptr(gamma), _ptr(force) if force is not None else None, _ptr(dmass), _ptr(ws),
+                         ctypes.c_size_t(nbytes), _stream())
+    L.check(rc, "sp_cg_force")
+    return gamma, force, dmass
+
+
+def tune_dslash(gauge: Gauge, prec) -> float:
+    """Pick the fastest launch shape of the half operator for this lattice and precision (ms per call)."""
+    lat = gauge.lat
+    dev = gauge.f64.device
+    a = torch.zeros(lat.vec_bytes(prec), dtype=torch.uint8, device=dev)
+    b = torch.zeros_like(a)
+    best = ctypes.c_double(0)
+    L.check(L.load().sp_tune_dslash(ctypes.byref(lat.geom), ctypes.byref(gauge.struct), _prec(prec), _ptr(a), _ptr(b),
+                                    _stream(), ctypes.byref(best)), "sp_tune_dslash")
+    return float(best.value)
+
+
+def tune_save(path: str):
+    L.check(L.load().sp_tune_save(path.encode()), "sp_tune_save")
+
+
+def tune_load(path: str):
+    L.check(L.load().sp_tune_load(path.encode()), "sp_tune_load")
+
+
+def release_cache():
+    L.load().sp_release_cache()

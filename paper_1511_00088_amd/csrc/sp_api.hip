@@ -1,0 +1,857 @@
+// C-ABI of libstagcg.so: argument checks, workspace layout, the CG drivers (single and batched), hipGraph
+// chunk replay, the launch autotuner and the force entry point.
+//
+// Solver schedule (mixed precision, after the FP64 set-up r = b - A x0):
+//   chunk = poll_chunk iterations of
+//             t = D_oe p                  (inner precision)
+//             q = m^2 p - D_eo t, Re<p,q>  -> alpha (device)
+//             x_lo += alpha p, r -= alpha q, |r|^2 -> beta, triggers (device)
+//             p = r + beta p
+//           then a reliable update when due (every ru_every iterations, when |r| drops below
+//           delta * |r at the last update|, at apparent convergence and at the iteration cap):
+//             x64 += x_lo, x_lo = 0; r = b - A x64 in FP64; r_lo = round(r); converged if |r| <= tol |b|
+//   The host replays chunks (one hipGraph launch each) and reads the device state once per chunk.
+// Plain FP64 CG is the same schedule with FP64 vectors, x updated in place and the FP64 true residual
+// computed only at apparent convergence.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <climits>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "../../include/sp_api.h"
+#include "sp_launch.h"
+
+using namespace sp;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                                  \
+    do {                                                                                               \
+        hipError_t e_ = (expr);                                                                        \
+        if (e_ != hipSuccess)                                                                          \
+            return fail(SP_ERR_HIP, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__,   \
+                        __LINE__);                                                                     \
+    } while (0)
+
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+bool valid_prec(int p) { return p >= SP_F64 && p <= SP_BF16; }
+
+int check_geom(const sp_geom* g, Geom* out) {
+    if (!g) return fail(SP_ERR_INVALID_ARG, "geometry is null");
+    long V = 1;
+    for (int mu = 0; mu < 4; ++mu) {
+        int L = g->dims[mu];
+        if (L < 2 || (L & 1)) return fail(SP_ERR_ODD_EXTENT, "extent %d of direction %d is odd or < 2", L, mu);
+        V *= L;
+    }
+    if (g->bc_t != 0 && g->bc_t != 1) return fail(SP_ERR_INVALID_ARG, "bc_t must be 0 or 1");
+    if (V / 2 >= (1L << 24)) return fail(SP_ERR_UNSUPPORTED, "lattice too large: V/2 = %ld >= 2^24", V / 2);
+    if (out) {
+        out->X = g->dims[0];
+        out->Y = g->dims[1];
+        out->Z = g->dims[2];
+        out->T = g->dims[3];
+        out->Xh = g->dims[0] / 2;
+        out->Vh = (int)(V / 2);
+        out->bc_t = g->bc_t;
+        out->rXh = 1.0f / (float)out->Xh;
+        out->rY = 1.0f / (float)out->Y;
+        out->rZ = 1.0f / (float)out->Z;
+    }
+    return SP_OK;
+}
+
+size_t link_bytes(int prec, int recon) {
+    if (prec == SP_F64) return recon == 18 ? 144 : 0;
+    if (prec == SP_F32) return recon == 18 ? 72 : recon == 12 ? 48 : 0;
+    return recon == 18 ? 36 : recon == 12 ? 24 : 0;
+}
+
+size_t vec_site_bytes(int prec) {
+    switch (prec) {
+        case SP_F64: return 48;
+        case SP_F32: return 24;
+        case SP_F16: return 16;
+        case SP_BF16: return 12;
+    }
+    return 0;
+}
+
+// ---------------------------------------------------------------------------------------------------
+// Tuned launch configurations
+// ---------------------------------------------------------------------------------------------------
+std::mutex g_mu;  // guards every cache below and the pinned staging buffers
+std::map<std::string, LaunchCfg> g_tune;
+
+std::string tune_key(const Geom& g, int lp, int recon, int vp) {
+    char b[128];
+    snprintf(b, sizeof b, "%dx%dx%dx%d/l%d/r%d/v%d", g.X, g.Y, g.Z, g.T, lp, recon, vp);
+    return b;
+}
+
+LaunchCfg tuned_cfg(const Geom& g, int lp, int recon, int vp) {
+    auto it = g_tune.find(tune_key(g, lp, recon, vp));
+    return it == g_tune.end() ? LaunchCfg{} : it->second;
+}
+
+// ---------------------------------------------------------------------------------------------------
+// Pinned host staging (control block upload, state polls)
+// ---------------------------------------------------------------------------------------------------
+struct Pinned {
+    void* p = nullptr;
+    size_t n = 0;
+    hipError_t ensure(size_t bytes) {
+        if (bytes <= n) return hipSuccess;
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        n = 0;
+        hipError_t e = hipHostMalloc(&p, bytes, hipHostMallocDefault);
+        if (e == hipSuccess) n = bytes;
+        return e;
+    }
+};
+Pinned g_upload, g_poll;
+
+struct Events {
+    hipEvent_t e[2] = {nullptr, nullptr};
+    hipError_t create() {
+        for (auto& x : e) {
+            hipError_t r = hipEventCreateWithFlags(&x, hipEventDisableTiming);
+            if (r) return r;
+        }
+        return hipSuccess;
+    }
+    ~Events() {
+        for (auto& x : e)
+            if (x) (void)hipEventDestroy(x);
+    }
+};
+
+// ---------------------------------------------------------------------------------------------------
+// Workspace layout of a solve over a list of systems grouped by (gauge, geometry)
+// ---------------------------------------------------------------------------------------------------
+struct GroupPlan {
+    Geom g;
+    const sp_gauge* U;
+    std::vector<int> sys;  // indices into the caller's system list
+    int nblk = 0, blk0 = 0;
+    size_t partials_off = 0;
+};
+
+struct Layout {
+    std::vector<GroupPlan> groups;
+    std::vector<size_t> sys_off;  // byte offset of each system's vector block
+    std::vector<int> sys_group;
+    size_t states_off = 0, tickets_off = 0, gdesc_off = 0, sdesc_off = 0, ctrl_bytes = 0;
+    size_t total = 0;
+    int inner = SP_F32, nbatch_rhs = 1;
+    int total_blocks = 0;
+    LaunchCfg cfg;
+};
+
+// Per-system vector block: B64 X64 T64 (48 B/site), XLO (24 B/site, mixed only), P R Q T (inner).
+size_t sys_block_bytes(int Vh, int inner, size_t slot_off[NSLOT]) {
+    size_t off = 0;
+    const size_t v64 = align256((size_t)Vh * 48);
+    const size_t vin = align256((size_t)Vh * vec_site_bytes(inner));
+    slot_off[S_B64] = off; off += v64;
+    slot_off[S_X64] = off; off += v64;
+    slot_off[S_T64] = off; off += v64;
+    slot_off[S_XLO] = off; if (inner != SP_F64) off += align256((size_t)Vh * 24);
+    slot_off[S_P] = off; off += vin;
+    slot_off[S_R] = off; off += vin;
+    slot_off[S_Q] = off; off += vin;
+    slot_off[S_T] = off; off += vin;
+    return off;
+}
+
+int params_inner(const sp_cg_params* prm) { return prm->inner; }
+
+// Groups systems and computes the workspace layout. n_rhs_max: 1 for a single solve, NB for batches.
+int make_layout(int nsys, const sp_system* systems, const sp_cg_params* prm, int n_rhs_max, Layout* L) {
+    if (nsys <= 0 || !systems) return fail(SP_ERR_INVALID_ARG, "no systems");
+    if (!prm) return fail(SP_ERR_INVALID_ARG, "params is null");
+    if (!valid_prec(prm->inner)) return fail(SP_ERR_INVALID_ARG, "bad inner precision %d", prm->inner);
+    L->inner = prm->inner;
+    L->nbatch_rhs = n_rhs_max;
+    L->groups.clear();
+    for (int i = 0; i < nsys; ++i) {
+        const sp_system& s = systems[i];
+        Geom g;
+        int rc = check_geom(s.g, &g);
+        if (rc) return rc;
+        if (!s.U) return fail(SP_ERR_INVALID_ARG, "system %d: gauge is null", i);
+        int gi = -1;
+        for (size_t k = 0; k < L->groups.size(); ++k) {
+            GroupPlan& G = L->groups[k];
+            if ((int)G.sys.size() < n_rhs_max && G.U->f64 == s.U->f64 && G.U->lo == s.U->lo &&
+                G.U->recon == s.U->recon && G.U->lo_prec == s.U->lo_prec && !memcmp(&G.g, &g, sizeof g)) {
+                gi = (int)k;
+                break;
+            }
+        }
+        if (gi < 0) {
+            GroupPlan G;
+            G.g = g;
+            G.U = s.U;
+            L->groups.push_back(G);
+            gi = (int)L->groups.size() - 1;
+        }
+        L->groups[gi].sys.push_back(i);
+    }
+    // launch shape: the tuned block size of the largest group's operator
+    int big = 0;
+    for (size_t k = 1; k < L->groups.size(); ++k)
+        if (L->groups[k].g.Vh > L->groups[big].g.Vh) big = (int)k;
+    {
+        const GroupPlan& G = L->groups[big];
+        const int lp = prm->inner == SP_F64 ? SP_F64 : G.U->lo_prec;
+        const int rc = prm->inner == SP_F64 ? 18 : G.U->recon;
+        L->cfg = tuned_cfg(G.g, lp, rc, prm->inner);
+    }
+    int blk = 0;
+    for (auto& G : L->groups) {
+        G.nblk = blocks_for(G.g.Vh, L->cfg.nt);
+        G.blk0 = blk;
+        blk += G.nblk;
+    }
+    L->total_blocks = blk;
+    // control block: states, tickets, descriptors
+    size_t off = 0;
+    L->states_off = off;
+    off += align256(sizeof(SolverState) * nsys);
+    L->tickets_off = off;
+    off += align256(64 * L->groups.size());
+    L->gdesc_off = off;
+    off += align256(sizeof(GroupDev) * L->groups.size());
+    L->sdesc_off = off;
+    off += align256(sizeof(SysDev) * nsys);
+    L->ctrl_bytes = off;
+    // partials: sized for the smallest block size so that retuning never overflows them
+    for (auto& G : L->groups) {
+        G.partials_off = off;
+        off += align256(sizeof(double) * (size_t)(2 * NB) * blocks_for(G.g.Vh, 64));
+    }
+    L->sys_off.assign(nsys, 0);
+    L->sys_group.assign(nsys, 0);
+    for (size_t k = 0; k < L->groups.size(); ++k)
+        for (int i : L->groups[k].sys) {
+            size_t so[NSLOT];
+            L->sys_off[i] = off;
+            L->sys_group[i] = (int)k;
+            off += sys_block_bytes(L->groups[k].g.Vh, L->inner, so);
+        }
+    L->total = off;
+    return SP_OK;
+}
+
+int check_gauge(const sp_gauge* U, int inner) {
+    if (!U->f64) return fail(SP_ERR_INVALID_ARG, "gauge f64 packing is null");
+    if (inner == SP_F64) return SP_OK;
+    if (!U->lo) return fail(SP_ERR_INVALID_ARG, "gauge lo packing is null");
+    if (U->lo_prec != inner)
+        return fail(SP_ERR_UNSUPPORTED, "gauge lo precision %d differs from the inner precision %d", U->lo_prec, inner);
+    if (U->recon != 18 && U->recon != 12) return fail(SP_ERR_INVALID_ARG, "recon must be 18 or 12");
+    return SP_OK;
+}
+
+// ---------------------------------------------------------------------------------------------------
+// Enqueue helpers
+// ---------------------------------------------------------------------------------------------------
+struct Plan {
+    int inner, lp, recon, nblocks;
+    LaunchCfg cfg;
+};
+
+template <class D>
+hipError_t enqueue_iterations(const D& d, const Plan& pl, int count, hipStream_t s) {
+    const int use64 = pl.inner == SP_F64;
+    for (int i = 0; i < count; ++i) {
+        hipError_t e;
+        if ((e = launch_dslash(d, pl.nblocks, pl.cfg, pl.lp, pl.recon, pl.inner, 1, S_P, S_T, 0, G_ITER, use64, s)))
+            return e;
+        if ((e = launch_dslash(d, pl.nblocks, pl.cfg, pl.lp, pl.recon, pl.inner, 0, S_T, S_Q, 1, G_ITER, use64, s)))
+            return e;
+        if ((e = launch_update(d, pl.nblocks, pl.cfg, pl.inner, s))) return e;
+        if ((e = launch_xpay(d, pl.nblocks, pl.cfg, pl.inner, G_ITER, s))) return e;
+    }
+    return hipSuccess;
+}
+
+template <class D>
+hipError_t enqueue_reliable(const D& d, const Plan& pl, hipStream_t s) {
+    hipError_t e;
+    if (pl.inner != SP_F64 && (e = launch_accum(d, pl.nblocks, pl.cfg, s))) return e;
+    if ((e = launch_dslash(d, pl.nblocks, pl.cfg, SP_F64, 18, SP_F64, 1, S_X64, S_T64, 0, G_RU, 1, s))) return e;
+    if ((e = launch_resid(d, pl.nblocks, pl.cfg, pl.inner, 0, s))) return e;
+    return launch_xpay(d, pl.nblocks, pl.cfg, pl.inner, G_XPAY, s);
+}
+
+template <class D>
+hipError_t enqueue_setup(const D& d, const Plan& pl, hipStream_t s) {
+    hipError_t e;
+    if ((e = launch_norm_b(d, pl.nblocks, pl.cfg, s))) return e;
+    if ((e = launch_dslash(d, pl.nblocks, pl.cfg, SP_F64, 18, SP_F64, 1, S_X64, S_T64, 0, G_ALIVE, 1, s))) return e;
+    return launch_resid(d, pl.nblocks, pl.cfg, pl.inner, 1, s);
+}
+
+template <class D>
+hipError_t enqueue_chunk(const D& d, const Plan& pl, int iters, hipStream_t s) {
+    hipError_t e = enqueue_iterations(d, pl, iters, s);
+    if (e) return e;
+    return enqueue_reliable(d, pl, s);
+}
+
+// ---------------------------------------------------------------------------------------------------
+// hipGraph cache: one executable graph per (descriptor bytes, plan, chunk length)
+// ---------------------------------------------------------------------------------------------------
+std::map<std::string, hipGraphExec_t> g_graphs;
+hipStream_t g_capture_stream = nullptr;
+int g_capture_device = -1;
+
+template <class D>
+std::string graph_key(const D& d, const Plan& pl, int iters) {
+    std::string k((const char*)&d, sizeof d);
+    k.append((const char*)&pl, sizeof pl);
+    k.append((const char*)&iters, sizeof iters);
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    k.append((const char*)&dev, sizeof dev);
+    return k;
+}
+
+void release_graphs();
+
+template <class D>
+hipError_t chunk_graph(const D& d, const Plan& pl, int iters, hipGraphExec_t* out) {
+    const std::string key = graph_key(d, pl, iters);
+    auto it = g_graphs.find(key);
+    if (it != g_graphs.end()) {
+        *out = it->second;
+        return hipSuccess;
+    }
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e) return e;
+    if (!g_capture_stream || g_capture_device != dev) {
+        if (g_capture_stream) (void)hipStreamDestroy(g_capture_stream);
+        g_capture_stream = nullptr;
+        if ((e = hipStreamCreateWithFlags(&g_capture_stream, hipStreamNonBlocking))) return e;
+        g_capture_device = dev;
+    }
+    if ((e = hipStreamBeginCapture(g_capture_stream, hipStreamCaptureModeThreadLocal))) return e;
+    hipError_t ee = enqueue_chunk(d, pl, iters, g_capture_stream);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(g_capture_stream, &graph);
+    if (ee) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return ee;
+    }
+    if (e) return e;
+    if (g_graphs.size() >= 64) release_graphs();
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e) return e;
+    g_graphs[key] = exec;
+    *out = exec;
+    return hipSuccess;
+}
+
+void release_graphs() {
+    for (auto& kv : g_graphs) (void)hipGraphExecDestroy(kv.second);
+    g_graphs.clear();
+}
+
+// ---------------------------------------------------------------------------------------------------
+// Solve driver shared by sp_cg_solve (DescSingle) and sp_cg_solve_batched (DescBatch)
+// ---------------------------------------------------------------------------------------------------
+SolverState initial_state(const sp_system& s, const sp_cg_params* prm) {
+    SolverState st;
+    memset(&st, 0, sizeof st);
+    st.tol2 = prm->tol * prm->tol;
+    st.delta2 = prm->delta > 0 ? prm->delta * prm->delta : 0.0;
+    st.m2 = s.mass * s.mass;
+    st.max_iter = prm->max_iter;
+    int every = prm->ru_every;
+    if (prm->inner == SP_F64) every = INT_MAX;
+    else if (every <= 0) every = 100;
+    st.ru_every = every;
+    st.restart = (prm->inner == SP_F16 || prm->inner == SP_BF16) ? 1 : 0;
+    return st;
+}
+
+int status_of(const SolverState& st) {
+    if (st.flags & ST_BREAKDOWN) return SP_ERR_BREAKDOWN;
+    if (st.flags & ST_CONVERGED) return SP_OK;
+    return SP_NOT_CONVERGED;
+}
+
+int solve_impl(int nsys, const sp_system* systems, const sp_cg_params* prm, sp_cg_stats* stats, void* ws,
+               size_t ws_bytes, hipStream_t stream, bool batched) {
+    const auto t0 = std::chrono::steady_clock::now();
+    if (!prm) return fail(SP_ERR_INVALID_ARG, "params is null");
+    if (!(prm->tol > 0.0) || !(prm->tol < 1.0)) return fail(SP_ERR_INVALID_ARG, "tol must be in (0, 1)");
+    if (prm->max_iter <= 0) return fail(SP_ERR_INVALID_ARG, "max_iter must be > 0");
+    if (prm->delta < 0.0 || prm->delta >= 1.0) return fail(SP_ERR_INVALID_ARG, "delta must be in [0, 1)");
+    for (int i = 0; i < nsys; ++i) {
+        if (!systems[i].b_e || !systems[i].x_e) return fail(SP_ERR_INVALID_ARG, "system %d: b or x is null", i);
+        if (!std::isfinite(systems[i].mass)) return fail(SP_ERR_INVALID_ARG, "system %d: mass not finite", i);
+        if (!systems[i].U) return fail(SP_ERR_INVALID_ARG, "system %d: gauge is null", i);
+        int rc = check_gauge(systems[i].U, prm->inner);
+        if (rc) return rc;
+    }
+    std::lock_guard<std::mutex> lock(g_mu);
+    Layout L;
+    int rc = make_layout(nsys, systems, prm, batched ? NB : 1, &L);
+    if (rc) return rc;
+    if (!ws) return fail(SP_ERR_WORKSPACE, "workspace is null");
+    if (ws_bytes < L.total) return fail(SP_ERR_WORKSPACE, "workspace %zu bytes < required %zu", ws_bytes, L.total);
+    if (((uintptr_t)ws) & 255) return fail(SP_ERR_INVALID_ARG, "workspace not 256-byte aligned");
+    char* base = (char*)ws;
+
+    // ---- control block on the host ----
+    HIP_TRY(g_upload.ensure(L.ctrl_bytes));
+    char* h = (char*)g_upload.p;
+    memset(h, 0, L.ctrl_bytes);
+    SolverState* hst = (SolverState*)(h + L.states_off);
+    for (int i = 0; i < nsys; ++i) hst[i] = initial_state(systems[i], prm);
+    GroupDev* hg = (GroupDev*)(h + L.gdesc_off);
+    SysDev* hs = (SysDev*)(h + L.sdesc_off);
+    int sys_counter = 0;
+    std::vector<int> order(nsys);  // descriptor index -> caller index
+    for (size_t k = 0; k < L.groups.size(); ++k) {
+        const GroupPlan& G = L.groups[k];
+        GroupDev gd;
+        memset(&gd, 0, sizeof gd);
+        gd.g = G.g;
+        gd.links64 = G.U->f64;
+        gd.links_lo = prm->inner == SP_F64 ? G.U->f64 : G.U->lo;
+        gd.partials = (double*)(base + G.partials_off);
+        gd.ticket = (unsigned*)(base + L.tickets_off + 64 * k);
+        gd.nrhs = (int)G.sys.size();
+        gd.sys0 = sys_counter;
+        gd.blk0 = G.blk0;
+        gd.nblk = G.nblk;
+        hg[k] = gd;
+        for (int i : G.sys) {
+            size_t so[NSLOT];
+            sys_block_bytes(G.g.Vh, L.inner, so);
+            SysDev sd;
+            for (int sl = 0; sl < NSLOT; ++sl) sd.v[sl] = base + L.sys_off[i] + so[sl];
+            sd.st = (SolverState*)(base + L.states_off) + i;
+            hs[sys_counter] = sd;
+            order[sys_counter] = i;
+            ++sys_counter;
+        }
+    }
+    HIP_TRY(hipMemcpyAsync(base, h, L.ctrl_bytes, hipMemcpyHostToDevice, stream));
+
+    // ---- pack b and x0 ----
+    for (int i = 0; i < nsys; ++i) {
+        const GroupPlan& G = L.groups[L.sys_group[i]];
+        size_t so[NSLOT];
+        sys_block_bytes(G.g.Vh, L.inner, so);
+        char* sb = base + L.sys_off[i];
+        HIP_TRY(launch_pack_vec(G.g.Vh, systems[i].b_e, SP_F64, sb + so[S_B64], stream));
+        if (prm->use_x0) HIP_TRY(launch_pack_vec(G.g.Vh, systems[i].x_e, SP_F64, sb + so[S_X64], stream));
+        else HIP_TRY(launch_zero(sb + so[S_X64], align256((size_t)G.g.Vh * 48), stream));
+        if (L.inner != SP_F64) HIP_TRY(launch_zero(sb + so[S_XLO], align256((size_t)G.g.Vh * 24), stream));
+    }
+
+    Plan pl;
+    pl.inner = L.inner;
+    pl.lp = L.inner == SP_F64 ? SP_F64 : L.groups[0].U->lo_prec;
+    pl.recon = L.inner == SP_F64 ? 18 : L.groups[0].U->recon;
+    pl.nblocks = L.total_blocks;
+    pl.cfg = L.cfg;
+    for (auto& G : L.groups)
+        if ((L.inner != SP_F64) && (G.U->recon != pl.recon || G.U->lo_prec != pl.lp))
+            return fail(SP_ERR_UNSUPPORTED, "all systems of a batch must share the link packing");
+
+    const int chunk = prm->poll_chunk > 0 ? prm->poll_chunk : 20;
+    HIP_TRY(g_poll.ensure(2 * sizeof(SolverState) * nsys));
+    SolverState* slots[2] = {(SolverState*)g_poll.p, (SolverState*)g_poll.p + nsys};
+
+    DescSingle ds;
+    DescBatch db;
+    memset(&ds, 0, sizeof ds);
+    memset(&db, 0, sizeof db);
+    if (!batched) {
+        ds.grp = hg[0];
+        ds.sys = hs[0];
+    } else {
+        db.grp = (const GroupDev*)(base + L.gdesc_off);
+        db.sys = (const SysDev*)(base + L.sdesc_off);
+        db.ngroups = (int)L.groups.size();
+    }
+    auto setup = [&]() { return batched ? enqueue_setup(db, pl, stream) : enqueue_setup(ds, pl, stream); };
+    HIP_TRY(setup());
+
+    hipGraphExec_t exec = nullptr;
+    if (prm->use_graph) {
+        hipError_t e = batched ? chunk_graph(db, pl, chunk, &exec) : chunk_graph(ds, pl, chunk, &exec);
+        HIP_TRY(e);
+    }
+    Events ev;
+    HIP_TRY(ev.create());
+    // Chunks are pipelined: chunk c is queued before the state written by chunk c-1 is inspected, so the
+    // GPU never waits for the host. Once every system is done, the chunk queued meanwhile finds all
+    // systems stopped and its kernels return at entry.
+    const long max_chunks = (long)prm->max_iter / chunk + 64;
+    SolverState* poll = nullptr;
+    for (long c = 0;; ++c) {
+        if (exec) HIP_TRY(hipGraphLaunch(exec, stream));
+        else HIP_TRY(batched ? enqueue_chunk(db, pl, chunk, stream) : enqueue_chunk(ds, pl, chunk, stream));
+        HIP_TRY(hipMemcpyAsync(slots[c & 1], base + L.states_off, sizeof(SolverState) * nsys, hipMemcpyDeviceToHost,
+                               stream));
+        HIP_TRY(hipEventRecord(ev.e[c & 1], stream));
+        if (c == 0) continue;
+        HIP_TRY(hipEventSynchronize(ev.e[(c - 1) & 1]));
+        SolverState* prev = slots[(c - 1) & 1];
+        bool all_done = true;
+        for (int i = 0; i < nsys; ++i) all_done &= (prev[i].flags & ST_DONE) != 0;
+        if (all_done) {
+            poll = prev;
+            break;
+        }
+        if (c > max_chunks) {
+            // cannot happen unless the device state is corrupted: every system stops at max_iter
+            return fail(SP_ERR_HIP, "solver did not stop after %ld chunks", c);
+        }
+    }
+
+    // ---- unpack x ----
+    for (int i = 0; i < nsys; ++i) {
+        const GroupPlan& G = L.groups[L.sys_group[i]];
+        size_t so[NSLOT];
+        sys_block_bytes(G.g.Vh, L.inner, so);
+        HIP_TRY(launch_unpack_vec(G.g.Vh, base + L.sys_off[i] + so[S_X64], SP_F64, systems[i].x_e, stream));
+    }
+    HIP_TRY(hipStreamSynchronize(stream));
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+
+    int worst = SP_OK;
+    for (int i = 0; i < nsys; ++i) {
+        const SolverState& st = poll[i];
+        const int s = status_of(st);
+        if (s < 0 && worst >= 0) worst = s;
+        else if (s > 0 && worst == SP_OK) worst = s;
+        if (stats) {
+            sp_cg_stats& o = stats[i];
+            o.iters = st.iter;
+            o.reliable_updates = st.ru_count;
+            o.converged = (st.flags & ST_CONVERGED) ? 1 : 0;
+            o.status = s;
+            o.true_rel_resid = st.bnorm2 > 0 ? std::sqrt(st.true_rho / st.bnorm2) : 0.0;
+            o.seconds = secs;
+        }
+    }
+    if (worst < 0) return fail(worst, "CG breakdown (Re<p,Ap> <= 0 or non-finite scalar)");
+    return worst;
+}
+
+}  // namespace
+
+// =====================================================================================================
+// C-ABI
+// =====================================================================================================
+extern "C" {
+
+int sp_version(void) { return 10000; }
+
+const char* sp_strerror(int code) {
+    switch (code) {
+        case SP_OK: return "ok";
+        case SP_NOT_CONVERGED: return "not converged";
+        case SP_ERR_INVALID_ARG: return "invalid argument";
+        case SP_ERR_ODD_EXTENT: return "lattice extent odd or < 2";
+        case SP_ERR_UNSUPPORTED: return "unsupported combination";
+        case SP_ERR_WORKSPACE: return "workspace missing or too small";
+        case SP_ERR_HIP: return "HIP runtime error";
+        case SP_ERR_BREAKDOWN: return "CG breakdown";
+    }
+    return "unknown status";
+}
+
+const char* sp_last_error(void) { return g_last_error.c_str(); }
+
+size_t sp_gauge_bytes(const sp_geom* g, int prec, int recon) {
+    Geom G;
+    if (check_geom(g, &G) || !valid_prec(prec)) return 0;
+    return 8 * (size_t)G.Vh * link_bytes(prec, recon);
+}
+
+int sp_gauge_pack(const sp_geom* g, const double* links_nat, int prec, int recon, void* out, void* stream) {
+    Geom G;
+    int rc = check_geom(g, &G);
+    if (rc) return rc;
+    if (!valid_prec(prec)) return fail(SP_ERR_INVALID_ARG, "bad precision %d", prec);
+    if (link_bytes(prec, recon) == 0) return fail(SP_ERR_UNSUPPORTED, "precision %d with recon %d", prec, recon);
+    if (!links_nat || !out) return fail(SP_ERR_INVALID_ARG, "null pointer");
+    HIP_TRY(launch_pack_gauge(G, links_nat, prec, recon, out, (hipStream_t)stream));
+    return SP_OK;
+}
+
+size_t sp_vec_bytes(const sp_geom* g, int prec) {
+    Geom G;
+    if (check_geom(g, &G) || !valid_prec(prec)) return 0;
+    return (size_t)G.Vh * vec_site_bytes(prec);
+}
+
+int sp_vec_pack(const sp_geom* g, const double* v_nat, int prec, void* out, void* stream) {
+    Geom G;
+    int rc = check_geom(g, &G);
+    if (rc) return rc;
+    if (!valid_prec(prec)) return fail(SP_ERR_INVALID_ARG, "bad precision %d", prec);
+    if (!v_nat || !out) return fail(SP_ERR_INVALID_ARG, "null pointer");
+    HIP_TRY(launch_pack_vec(G.Vh, v_nat, prec, out, (hipStream_t)stream));
+    return SP_OK;
+}
+
+int sp_vec_unpack(const sp_geom* g, const void* v, int prec, double* v_nat, void* stream) {
+    Geom G;
+    int rc = check_geom(g, &G);
+    if (rc) return rc;
+    if (!valid_prec(prec)) return fail(SP_ERR_INVALID_ARG, "bad precision %d", prec);
+    if (!v || !v_nat) return fail(SP_ERR_INVALID_ARG, "null pointer");
+    HIP_TRY(launch_unpack_vec(G.Vh, v, prec, v_nat, (hipStream_t)stream));
+    return SP_OK;
+}
+
+static int dslash_desc(const sp_geom* g, const sp_gauge* U, int prec, const void* in, void* out, int out_parity,
+                       Geom* G, DescSingle* d, int* lp, int* recon) {
+    int rc = check_geom(g, G);
+    if (rc) return rc;
+    if (!valid_prec(prec)) return fail(SP_ERR_INVALID_ARG, "bad precision %d", prec);
+    if (!U || !in || !out) return fail(SP_ERR_INVALID_ARG, "null pointer");
+    if (out_parity != 0 && out_parity != 1) return fail(SP_ERR_INVALID_ARG, "out_parity must be 0 or 1");
+    if (in == out) return fail(SP_ERR_INVALID_ARG, "in and out must differ");
+    const void* links;
+    if (prec == SP_F64) {
+        links = U->f64;
+        *lp = SP_F64;
+        *recon = 18;
+    } else {
+        if (U->lo_prec != prec) return fail(SP_ERR_UNSUPPORTED, "gauge lo precision %d != %d", U->lo_prec, prec);
+        if (U->recon != 18 && U->recon != 12) return fail(SP_ERR_INVALID_ARG, "recon must be 18 or 12");
+        links = U->lo;
+        *lp = prec;
+        *recon = U->recon;
+    }
+    if (!links) return fail(SP_ERR_INVALID_ARG, "gauge field of precision %d is null", prec);
+    memset(d, 0, sizeof *d);
+    d->grp.g = *G;
+    d->grp.links_lo = links;
+    d->grp.links64 = links;
+    d->grp.nrhs = 1;
+    d->sys.v[S_P] = const_cast<void*>(in);
+    d->sys.v[S_T] = out;
+    return SP_OK;
+}
+
+int sp_dslash(const sp_geom* g, const sp_gauge* U, int prec, const void* in, void* out, int out_parity, void* stream) {
+    Geom G;
+    DescSingle d;
+    int lp, recon;
+    int rc = dslash_desc(g, U, prec, in, out, out_parity, &G, &d, &lp, &recon);
+    if (rc) return rc;
+    LaunchCfg c;
+    {
+        std::lock_guard<std::mutex> lock(g_mu);
+        c = tuned_cfg(G, lp, recon, prec);
+    }
+    const int nb = blocks_for(G.Vh, c.nt);
+    d.grp.nblk = nb;
+    HIP_TRY(launch_dslash(d, nb, c, lp, recon, prec, out_parity, S_P, S_T, 0, G_NONE, prec == SP_F64,
+                          (hipStream_t)stream));
+    return SP_OK;
+}
+
+int sp_tune_dslash(const sp_geom* g, const sp_gauge* U, int prec, void* in, void* out, void* stream, double* best_ms) {
+    Geom G;
+    DescSingle d;
+    int lp, recon;
+    int rc = dslash_desc(g, U, prec, in, out, 1, &G, &d, &lp, &recon);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    const int nts[3] = {64, 128, 256};
+    LaunchCfg best;
+    float best_t = 1e30f;
+    const int reps = 20;
+    for (int remap = 0; remap <= 1; ++remap)
+        for (int nt : nts) {
+            LaunchCfg c;
+            c.nt = nt;
+            c.remap = remap;
+            const int nb = blocks_for(G.Vh, nt);
+            d.grp.nblk = nb;
+            for (int w = 0; w < 3; ++w)
+                HIP_TRY(launch_dslash(d, nb, c, lp, recon, prec, 1, S_P, S_T, 0, G_NONE, prec == SP_F64, s));
+            HIP_TRY(hipEventRecord(e0, s));
+            for (int k = 0; k < reps; ++k)
+                HIP_TRY(launch_dslash(d, nb, c, lp, recon, prec, 1, S_P, S_T, 0, G_NONE, prec == SP_F64, s));
+            HIP_TRY(hipEventRecord(e1, s));
+            HIP_TRY(hipEventSynchronize(e1));
+            float ms = 0;
+            HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+            ms /= reps;
+            if (ms < best_t) {
+                best_t = ms;
+                best = c;
+            }
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    {
+        std::lock_guard<std::mutex> lock(g_mu);
+        g_tune[tune_key(G, lp, recon, prec)] = best;
+    }
+    if (best_ms) *best_ms = best_t;
+    return SP_OK;
+}
+
+int sp_tune_save(const char* path) {
+    if (!path) return fail(SP_ERR_INVALID_ARG, "path is null");
+    std::lock_guard<std::mutex> lock(g_mu);
+    std::ofstream f(path);
+    if (!f) return fail(SP_ERR_INVALID_ARG, "cannot write %s", path);
+    f << "{\n";
+    size_t i = 0;
+    for (auto& kv : g_tune) {
+        f << "  \"" << kv.first << "\": {\"nt\": " << kv.second.nt << ", \"remap\": " << kv.second.remap << "}"
+          << (++i < g_tune.size() ? ",\n" : "\n");
+    }
+    f << "}\n";
+    return SP_OK;
+}
+
+int sp_tune_load(const char* path) {
+    if (!path) return fail(SP_ERR_INVALID_ARG, "path is null");
+    std::ifstream f(path);
+    if (!f) return fail(SP_ERR_INVALID_ARG, "cannot read %s", path);
+    std::stringstream ss;
+    ss << f.rdbuf();
+    const std::string txt = ss.str();
+    std::lock_guard<std::mutex> lock(g_mu);
+    size_t pos = 0;
+    int n = 0;
+    while ((pos = txt.find('"', pos)) != std::string::npos) {
+        const size_t end = txt.find('"', pos + 1);
+        if (end == std::string::npos) break;
+        const std::string key = txt.substr(pos + 1, end - pos - 1);
+        LaunchCfg c;
+        int nt = 0, remap = 0;
+        const size_t brace = txt.find('{', end);
+        if (brace == std::string::npos) break;
+        if (sscanf(txt.c_str() + brace, "{\"nt\": %d, \"remap\": %d}", &nt, &remap) != 2)
+            return fail(SP_ERR_INVALID_ARG, "malformed tuning entry for %s", key.c_str());
+        if (nt != 64 && nt != 128 && nt != 256) return fail(SP_ERR_INVALID_ARG, "bad block size %d", nt);
+        c.nt = nt;
+        c.remap = remap ? 1 : 0;
+        g_tune[key] = c;
+        ++n;
+        pos = txt.find('}', brace) + 1;
+    }
+    return SP_OK;
+}
+
+void sp_release_cache(void) {
+    std::lock_guard<std::mutex> lock(g_mu);
+    release_graphs();
+    g_tune.clear();
+}
+
+size_t sp_cg_workspace_bytes(int nsys, const sp_system* systems, const sp_cg_params* params) {
+    std::lock_guard<std::mutex> lock(g_mu);
+    Layout L;
+    if (make_layout(nsys, systems, params, nsys > 1 ? NB : 1, &L)) return 0;
+    return L.total;
+}
+
+int sp_cg_solve(const sp_geom* g, const sp_gauge* U, double mass, const double* b_e, double* x_e,
+                const sp_cg_params* params, sp_cg_stats* stats, void* ws, size_t ws_bytes, void* stream) {
+    sp_system s;
+    s.g = g;
+    s.U = U;
+    s.mass = mass;
+    s.b_e = b_e;
+    s.x_e = x_e;
+    return solve_impl(1, &s, params, stats, ws, ws_bytes, (hipStream_t)stream, false);
+}
+
+int sp_cg_solve_batched(int nsys, const sp_system* systems, const sp_cg_params* params, sp_cg_stats* stats,
+                        void* ws, size_t ws_bytes, void* stream) {
+    if (nsys <= 0 || !systems) return fail(SP_ERR_INVALID_ARG, "no systems");
+    return solve_impl(nsys, systems, params, stats, ws, ws_bytes, (hipStream_t)stream, true);
+}
+
+size_t sp_force_workspace_bytes(const sp_geom* g) {
+    Geom G;
+    if (check_geom(g, &G)) return 0;
+    return 4 * align256((size_t)G.Vh * 48) + align256(sizeof(double) * (size_t)mass_grad_blocks(G)) + 256;
+}
+
+int sp_cg_force(const sp_geom* g, const sp_gauge* U, double mass, const double* x_e, const double* lambda_e,
+                double* gamma, double* force, double* grad_mass, void* ws, size_t ws_bytes, void* stream) {
+    Geom G;
+    int rc = check_geom(g, &G);
+    if (rc) return rc;
+    if (!U || !U->f64 || !x_e || !lambda_e || !gamma) return fail(SP_ERR_INVALID_ARG, "null pointer");
+    if (!std::isfinite(mass)) return fail(SP_ERR_INVALID_ARG, "mass not finite");
+    if (!ws) return fail(SP_ERR_WORKSPACE, "workspace is null");
+    if (ws_bytes < sp_force_workspace_bytes(g)) return fail(SP_ERR_WORKSPACE, "workspace too small");
+    if (((uintptr_t)ws) & 255) return fail(SP_ERR_INVALID_ARG, "workspace not 256-byte aligned");
+    hipStream_t s = (hipStream_t)stream;
+    char* base = (char*)ws;
+    const size_t v = align256((size_t)G.Vh * 48);
+    void* xp = base;
+    void* lp = base + v;
+    void* yx = base + 2 * v;
+    void* yl = base + 3 * v;
+    double* partials = (double*)(base + 4 * v);
+    unsigned* ticket = (unsigned*)(base + 4 * v + align256(sizeof(double) * (size_t)mass_grad_blocks(G)));
+    HIP_TRY(launch_pack_vec(G.Vh, x_e, SP_F64, xp, s));
+    HIP_TRY(launch_pack_vec(G.Vh, lambda_e, SP_F64, lp, s));
+    HIP_TRY(launch_zero(ticket, 256, s));
+    sp_gauge Ug = *U;
+    Ug.lo = U->f64;
+    Ug.lo_prec = SP_F64;
+    rc = sp_dslash(g, &Ug, SP_F64, xp, yx, 1, stream);
+    if (rc) return rc;
+    rc = sp_dslash(g, &Ug, SP_F64, lp, yl, 1, stream);
+    if (rc) return rc;
+    HIP_TRY(launch_force(G, U->f64, xp, lp, yx, yl, gamma, force, s));
+    if (grad_mass) HIP_TRY(launch_mass_grad(G, mass, xp, lp, partials, ticket, grad_mass, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return SP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,585 @@
+// Device building blocks for the staggered even-odd CG on CDNA4 (gfx950): complex / SU(3) arithmetic,
+// structure-of-arrays storage formats, checkerboard geometry, wave64 reductions and the device-resident
+// solver state.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sp {
+
+enum Prec : int { F64 = 0, F32 = 1, F16 = 2, BF16 = 3 };
+
+// ------------------------------------------------------------------------------------------------------
+// Complex colour vectors and 3x3 links
+// ------------------------------------------------------------------------------------------------------
+template <class R>
+struct Cx {
+    R re, im;
+};
+
+template <class R>
+struct Vec3 {
+    Cx<R> c[3];
+};
+
+template <class R>
+struct Su3 {
+    Cx<R> e[3][3];
+};
+
+template <class R>
+__device__ __forceinline__ Vec3<R> vzero() {
+    Vec3<R> v;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) v.c[i].re = v.c[i].im = R(0);
+    return v;
+}
+
+// acc += s * (U v)
+template <class R>
+__device__ __forceinline__ void mv_acc(Vec3<R>& acc, const Su3<R>& U, const Vec3<R>& v, R s) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        R re = R(0), im = R(0);
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            re += U.e[i][j].re * v.c[j].re - U.e[i][j].im * v.c[j].im;
+            im += U.e[i][j].re * v.c[j].im + U.e[i][j].im * v.c[j].re;
+        }
+        acc.c[i].re += s * re;
+        acc.c[i].im += s * im;
+    }
+}
+
+// acc += s * (U^dag v)
+template <class R>
+__device__ __forceinline__ void mdv_acc(Vec3<R>& acc, const Su3<R>& U, const Vec3<R>& v, R s) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        R re = R(0), im = R(0);
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            re += U.e[j][i].re * v.c[j].re + U.e[j][i].im * v.c[j].im;
+            im += U.e[j][i].re * v.c[j].im - U.e[j][i].im * v.c[j].re;
+        }
+        acc.c[i].re += s * re;
+        acc.c[i].im += s * im;
+    }
+}
+
+// Third row of an SU(3) matrix from the first two: row2 = conj(row0 x row1).
+template <class R>
+__device__ __forceinline__ void rebuild_row2(Su3<R>& U) {
+    auto cross = [](Cx<R> a, Cx<R> b, Cx<R> c, Cx<R> d) {  // conj(a*b - c*d)
+        Cx<R> r;
+        r.re = (a.re * b.re - a.im * b.im) - (c.re * d.re - c.im * d.im);
+        r.im = -((a.re * b.im + a.im * b.re) - (c.re * d.im + c.im * d.re));
+        return r;
+    };
+    U.e[2][0] = cross(U.e[0][1], U.e[1][2], U.e[0][2], U.e[1][1]);
+    U.e[2][1] = cross(U.e[0][2], U.e[1][0], U.e[0][0], U.e[1][2]);
+    U.e[2][2] = cross(U.e[0][0], U.e[1][1], U.e[0][1], U.e[1][0]);
+}
+
+// ------------------------------------------------------------------------------------------------------
+// Scalar conversions for 16-bit storage (round to nearest even)
+// ------------------------------------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t f32_to_bf16_bits(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (u >> 16) | 0x40u;  // quiet NaN
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return u >> 16;
+}
+__device__ __forceinline__ float bf16_bits_to_f32(uint32_t b) { return __uint_as_float(b << 16); }
+
+__device__ __forceinline__ uint32_t f32_to_f16_bits(float f) {
+    _Float16 h = (_Float16)f;
+    return (uint32_t)__builtin_bit_cast(uint16_t, h);
+}
+__device__ __forceinline__ float f16_bits_to_f32(uint32_t b) {
+    return (float)__builtin_bit_cast(_Float16, (uint16_t)(b & 0xffffu));
+}
+
+template <int P>
+__device__ __forceinline__ uint32_t pack2(float a, float b) {
+    if constexpr (P == F16)
+        return f32_to_f16_bits(a) | (f32_to_f16_bits(b) << 16);
+    else
+        return f32_to_bf16_bits(a) | (f32_to_bf16_bits(b) << 16);
+}
+template <int P>
+__device__ __forceinline__ float unpack_lo(uint32_t w) {
+    if constexpr (P == F16) return f16_bits_to_f32(w);
+    else return bf16_bits_to_f32(w & 0xffffu);
+}
+template <int P>
+__device__ __forceinline__ float unpack_hi(uint32_t w) {
+    if constexpr (P == F16) return f16_bits_to_f32(w >> 16);
+    else return bf16_bits_to_f32(w >> 16);
+}
+
+template <int P>
+struct Real {
+    using T = float;
+};
+template <>
+struct Real<F64> {
+    using T = double;
+};
+
+// ------------------------------------------------------------------------------------------------------
+// Vector storage: one parity-half vector of Vh sites, 3 complex colours per site, as planes so that a
+// wavefront reads 64 consecutive sites with one wide load per plane.
+//   F64 : 3 planes of double2 (one per colour)                                        48 B/site
+//   F32 : plane float4 (colours 0,1) + plane float2 (colour 2)                         24 B/site
+//   F16 : plane uint2 (4 halves: colours 0,1) + plane uint (colour 2) + plane float
+//         norm; stored value = half * norm, norm = max |component| of the site           16 B/site
+//   BF16: plane uint2 + plane uint, unscaled                                          12 B/site
+// ------------------------------------------------------------------------------------------------------
+template <int P>
+struct VecFmt;
+
+template <>
+struct VecFmt<F64> {
+    static constexpr int bytes = 48;
+    __device__ static Vec3<double> load(const void* base, int Vh, int cb) {
+        const double2* p = (const double2*)base;
+        Vec3<double> v;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            double2 a = p[(size_t)c * Vh + cb];
+            v.c[c].re = a.x;
+            v.c[c].im = a.y;
+        }
+        return v;
+    }
+    __device__ static void store(void* base, int Vh, int cb, const Vec3<double>& v) {
+        double2* p = (double2*)base;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) p[(size_t)c * Vh + cb] = make_double2(v.c[c].re, v.c[c].im);
+    }
+};
+
+template <>
+struct VecFmt<F32> {
+    static constexpr int bytes = 24;
+    __device__ static Vec3<float> load(const void* base, int Vh, int cb) {
+        const float4* p4 = (const float4*)base;
+        const float2* p2 = (const float2*)(p4 + Vh);
+        float4 a = p4[cb];
+        float2 b = p2[cb];
+        Vec3<float> v;
+        v.c[0].re = a.x; v.c[0].im = a.y; v.c[1].re = a.z; v.c[1].im = a.w;
+        v.c[2].re = b.x; v.c[2].im = b.y;
+        return v;
+    }
+    __device__ static void store(void* base, int Vh, int cb, const Vec3<float>& v) {
+        float4* p4 = (float4*)base;
+        float2* p2 = (float2*)(p4 + Vh);
+        p4[cb] = make_float4(v.c[0].re, v.c[0].im, v.c[1].re, v.c[1].im);
+        p2[cb] = make_float2(v.c[2].re, v.c[2].im);
+    }
+};
+
+template <int P>
+struct VecFmt16 {
+    static constexpr bool scaled = (P == F16);
+    static constexpr int bytes = scaled ? 16 : 12;
+    __device__ static Vec3<float> load(const void* base, int Vh, int cb) {
+        const uint2* pa = (const uint2*)base;
+        const uint32_t* pb = (const uint32_t*)(pa + Vh);
+        uint2 a = pa[cb];
+        uint32_t b = pb[cb];
+        float s = 1.0f;
+        if constexpr (scaled) s = ((const float*)(pb + Vh))[cb];
+        Vec3<float> v;
+        v.c[0].re = s * unpack_lo<P>(a.x); v.c[0].im = s * unpack_hi<P>(a.x);
+        v.c[1].re = s * unpack_lo<P>(a.y); v.c[1].im = s * unpack_hi<P>(a.y);
+        v.c[2].re = s * unpack_lo<P>(b);   v.c[2].im = s * unpack_hi<P>(b);
+        return v;
+    }
+    __device__ static void store(void* base, int Vh, int cb, const Vec3<float>& v) {
+        uint2* pa = (uint2*)base;
+        uint32_t* pb = (uint32_t*)(pa + Vh);
+        float inv = 1.0f;
+        if constexpr (scaled) {
+            float m = 0.0f;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) m = fmaxf(m, fmaxf(fabsf(v.c[c].re), fabsf(v.c[c].im)));
+            ((float*)(pb + Vh))[cb] = m;
+            inv = m > 0.0f ? 1.0f / m : 0.0f;
+        }
+        pa[cb] = make_uint2(pack2<P>(inv * v.c[0].re, inv * v.c[0].im), pack2<P>(inv * v.c[1].re, inv * v.c[1].im));
+        pb[cb] = pack2<P>(inv * v.c[2].re, inv * v.c[2].im);
+    }
+};
+template <>
+struct VecFmt<F16> : VecFmt16<F16> {};
+template <>
+struct VecFmt<BF16> : VecFmt16<BF16> {};
+
+// ------------------------------------------------------------------------------------------------------
+// Link storage. The packed field is 8 blocks (parity q = 0,1) x (mu = 0..3), block (q, mu) holding
+// U_mu(n) for the Vh sites n of parity q in cb order, as planes:
+//   F64  r18: 9 planes double2                         144 B/link
+//   F32  r18: 4 planes float4 + 1 plane float2          72 B/link
+//   F32  r12: 3 planes float4 (rows 0,1)                48 B/link
+//   16b  r18: 2 planes uint4 (16 values) + 1 plane uint  36 B/link
+//   16b  r12: 1 plane uint4 + 1 plane uint2             24 B/link
+// Real parts and imaginary parts alternate, row-major: e00.re e00.im e01.re ... e22.im.
+// ------------------------------------------------------------------------------------------------------
+template <int P, int RECON>
+struct LinkFmt;
+
+template <>
+struct LinkFmt<F64, 18> {
+    static constexpr int bytes = 144;
+    __device__ static Su3<double> load(const void* blk, int Vh, int cb) {
+        const double2* p = (const double2*)blk;
+        Su3<double> U;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            double2 a = p[(size_t)k * Vh + cb];
+            U.e[k / 3][k % 3].re = a.x;
+            U.e[k / 3][k % 3].im = a.y;
+        }
+        return U;
+    }
+    __device__ static void store(void* blk, int Vh, int cb, const double* r) {
+        double2* p = (double2*)blk;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) p[(size_t)k * Vh + cb] = make_double2(r[2 * k], r[2 * k + 1]);
+    }
+};
+
+template <int RECON>
+struct LinkFmtF32 {
+    static constexpr int nq = RECON == 18 ? 4 : 3;  // float4 planes
+    static constexpr int bytes = RECON == 18 ? 72 : 48;
+    __device__ static Su3<float> load(const void* blk, int Vh, int cb) {
+        const float4* p = (const float4*)blk;
+        float f[18];
+#pragma unroll
+        for (int k = 0; k < nq; ++k) {
+            float4 a = p[(size_t)k * Vh + cb];
+            f[4 * k] = a.x; f[4 * k + 1] = a.y; f[4 * k + 2] = a.z; f[4 * k + 3] = a.w;
+        }
+        if constexpr (RECON == 18) {
+            float2 b = ((const float2*)(p + (size_t)4 * Vh))[cb];
+            f[16] = b.x; f[17] = b.y;
+        }
+        Su3<float> U;
+#pragma unroll
+        for (int k = 0; k < RECON / 2; ++k) {
+            U.e[k / 3][k % 3].re = f[2 * k];
+            U.e[k / 3][k % 3].im = f[2 * k + 1];
+        }
+        if constexpr (RECON == 12) rebuild_row2(U);
+        return U;
+    }
+    __device__ static void store(void* blk, int Vh, int cb, const double* r) {
+        float4* p = (float4*)blk;
+#pragma unroll
+        for (int k = 0; k < nq; ++k)
+            p[(size_t)k * Vh + cb] = make_float4((float)r[4 * k], (float)r[4 * k + 1], (float)r[4 * k + 2], (float)r[4 * k + 3]);
+        if constexpr (RECON == 18) ((float2*)(p + (size_t)4 * Vh))[cb] = make_float2((float)r[16], (float)r[17]);
+    }
+};
+template <>
+struct LinkFmt<F32, 18> : LinkFmtF32<18> {};
+template <>
+struct LinkFmt<F32, 12> : LinkFmtF32<12> {};
+
+template <int P, int RECON>
+struct LinkFmt16 {
+    static constexpr int bytes = RECON == 18 ? 36 : 24;
+    __device__ static Su3<float> load(const void* blk, int Vh, int cb) {
+        const uint4* p = (const uint4*)blk;
+        uint32_t w[9];
+        uint4 a = p[cb];
+        w[0] = a.x; w[1] = a.y; w[2] = a.z; w[3] = a.w;
+        if constexpr (RECON == 18) {
+            uint4 b = p[(size_t)Vh + cb];
+            w[4] = b.x; w[5] = b.y; w[6] = b.z; w[7] = b.w;
+            w[8] = ((const uint32_t*)(p + (size_t)2 * Vh))[cb];
+        } else {
+            uint2 b = ((const uint2*)(p + (size_t)Vh))[cb];
+            w[4] = b.x; w[5] = b.y;
+        }
+        Su3<float> U;
+#pragma unroll
+        for (int k = 0; k < RECON / 2; ++k) {
+            U.e[k / 3][k % 3].re = unpack_lo<P>(w[k]);
+            U.e[k / 3][k % 3].im = unpack_hi<P>(w[k]);
+        }
+        if constexpr (RECON == 12) rebuild_row2(U);
+        return U;
+    }
+    __device__ static void store(void* blk, int Vh, int cb, const double* r) {
+        uint32_t w[9];
+#pragma unroll
+        for (int k = 0; k < RECON / 2; ++k) w[k] = pack2<P>((float)r[2 * k], (float)r[2 * k + 1]);
+        uint4* p = (uint4*)blk;
+        p[cb] = make_uint4(w[0], w[1], w[2], w[3]);
+        if constexpr (RECON == 18) {
+            p[(size_t)Vh + cb] = make_uint4(w[4], w[5], w[6], w[7]);
+            ((uint32_t*)(p + (size_t)2 * Vh))[cb] = w[8];
+        } else {
+            ((uint2*)(p + (size_t)Vh))[cb] = make_uint2(w[4], w[5]);
+        }
+    }
+};
+template <>
+struct LinkFmt<F16, 18> : LinkFmt16<F16, 18> {};
+template <>
+struct LinkFmt<F16, 12> : LinkFmt16<F16, 12> {};
+template <>
+struct LinkFmt<BF16, 18> : LinkFmt16<BF16, 18> {};
+template <>
+struct LinkFmt<BF16, 12> : LinkFmt16<BF16, 12> {};
+
+// Address of block (q, mu) of a packed gauge field.
+template <class LF>
+__device__ __forceinline__ const char* link_block(const void* links, int Vh, int q, int mu) {
+    return (const char*)links + (size_t)(q * 4 + mu) * (size_t)Vh * LF::bytes;
+}
+
+// ------------------------------------------------------------------------------------------------------
+// Checkerboard geometry
+// ------------------------------------------------------------------------------------------------------
+struct Geom {
+    int X, Y, Z, T;
+    int Xh;   // X / 2
+    int Vh;   // X*Y*Z*T / 2
+    int bc_t; // 1: antiperiodic in t
+    float rXh, rY, rZ;  // reciprocals for the index division
+};
+
+// floor(a / d) for 0 <= a < 2^24, 1 <= d: the float estimate is within one of the quotient.
+__host__ __device__ __forceinline__ int divq(int a, int d, float rd) {
+    int q = (int)((float)a * rd);
+    int r = a - q * d;
+    q += (r >= d) - (r < 0);
+    return q;
+}
+
+struct Site {
+    int cb;
+    int x, y, z, t;
+    int row;  // cb - x/2: first cb of this (y,z,t) row
+};
+
+__host__ __device__ __forceinline__ Site site_of(const Geom& g, int p, int cb) {
+    Site s;
+    s.cb = cb;
+    int r = divq(cb, g.Xh, g.rXh);
+    int xh = cb - r * g.Xh;
+    int r2 = divq(r, g.Y, g.rY);
+    s.y = r - r2 * g.Y;
+    s.t = divq(r2, g.Z, g.rZ);
+    s.z = r2 - s.t * g.Z;
+    s.x = 2 * xh + ((p + s.y + s.z + s.t) & 1);
+    s.row = cb - xh;
+    return s;
+}
+
+// cb index of n + mu (dir = +1) or n - mu (dir = -1); the neighbour has the opposite parity.
+__host__ __device__ __forceinline__ int nbr(const Geom& g, const Site& s, int mu, int dir) {
+    if (mu == 0) {
+        int x1 = dir > 0 ? (s.x + 1 == g.X ? 0 : s.x + 1) : (s.x == 0 ? g.X - 1 : s.x - 1);
+        return s.row + (x1 >> 1);
+    }
+    int stride, c, L;
+    if (mu == 1) { stride = g.Xh; c = s.y; L = g.Y; }
+    else if (mu == 2) { stride = g.Xh * g.Y; c = s.z; L = g.Z; }
+    else { stride = g.Xh * g.Y * g.Z; c = s.t; L = g.T; }
+    if (dir > 0) return c == L - 1 ? s.cb - (L - 1) * stride : s.cb + stride;
+    return c == 0 ? s.cb + (L - 1) * stride : s.cb - stride;
+}
+
+// eta_mu(n): +1 or -1
+__host__ __device__ __forceinline__ float eta_sign(const Site& s, int mu) {
+    int e = mu == 0 ? 0 : mu == 1 ? s.x : mu == 2 ? s.x + s.y : s.x + s.y + s.z;
+    return (e & 1) ? -1.0f : 1.0f;
+}
+
+// ------------------------------------------------------------------------------------------------------
+// The half operator at one site:
+//   out(n) = 1/2 sum_mu eta_mu(n) [ s_f U_mu(n) in(n+mu) - s_b U_mu(n-mu)^dag in(n-mu) ]
+// with s_f, s_b the antiperiodic-time signs of the two links. Links of parity p are the forward links;
+// the backward link U_mu(n-mu) sits at the neighbour's cb in the parity 1-p block.
+// ------------------------------------------------------------------------------------------------------
+template <int LP, int RECON, int VP>
+__device__ __forceinline__ Vec3<typename Real<VP>::T> dslash_site(const Geom& g, const void* links, const void* in,
+                                                                  int p, const Site& s) {
+    using R = typename Real<VP>::T;
+    using LF = LinkFmt<LP, RECON>;
+    using VF = VecFmt<VP>;
+    Vec3<R> acc = vzero<R>();
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+        R e = (R)eta_sign(s, mu);
+        R sf = e, sb = e;
+        if (mu == 3 && g.bc_t) {
+            if (s.t == g.T - 1) sf = -sf;
+            if (s.t == 0) sb = -sb;
+        }
+        int nf = nbr(g, s, mu, +1);
+        int nb = nbr(g, s, mu, -1);
+        Su3<R> Uf = LF::load(link_block<LF>(links, g.Vh, p, mu), g.Vh, s.cb);
+        Vec3<R> vf = VF::load(in, g.Vh, nf);
+        Su3<R> Ub = LF::load(link_block<LF>(links, g.Vh, 1 - p, mu), g.Vh, nb);
+        Vec3<R> vb = VF::load(in, g.Vh, nb);
+        mv_acc(acc, Uf, vf, sf);
+        mdv_acc(acc, Ub, vb, -sb);
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        acc.c[i].re *= R(0.5);
+        acc.c[i].im *= R(0.5);
+    }
+    return acc;
+}
+
+// ------------------------------------------------------------------------------------------------------
+// Reductions (FP64, fixed order: deterministic for a fixed launch shape)
+// ------------------------------------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Sums NV values per thread across the block; results valid in thread 0. blockDim.x <= 1024.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV]) {
+    __shared__ double sm[NV][16];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] = wave_sum(v[k]);
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) sm[k][wid] = v[k];
+    }
+    __syncthreads();
+    if (wid == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            double a = lane < nw ? sm[k][lane] : 0.0;
+            v[k] = wave_sum(a);
+        }
+    }
+    __syncthreads();
+}
+
+// ------------------------------------------------------------------------------------------------------
+// Device-resident CG state of one system. Written only by the last block of a reducing kernel (after
+// every block of that launch has read it) and read by later launches, so every block of a launch sees
+// the same values.
+// ------------------------------------------------------------------------------------------------------
+enum : int {
+    ST_DONE = 1,        // stop: every kernel of this system returns at entry
+    ST_BREAKDOWN = 2,   // Re<p,Ap> <= 0 or a non-finite scalar
+    ST_PENDING = 4,     // iterations paused until the next reliable update
+    ST_MAXIT = 8,       // iteration cap reached
+    ST_STALL = 16,      // true residual stopped improving
+    ST_CONVERGED = 32,  // true residual <= tol |b|
+    ST_XPAY_DUE = 64,   // the paused iteration's p = r + beta p is still to be done
+};
+
+struct alignas(64) SolverState {
+    double rho;       // |r|^2 entering the current iteration
+    double alpha, beta, pq, rho_new;
+    double xpay_a;    // p = xpay_a r + beta p after a reliable update
+    double rr_ru;     // true |r|^2 at the last reliable update (delta trigger)
+    double bnorm2;    // |b|^2
+    double stop2;     // tol^2 |b|^2
+    double tol2;      // tol^2
+    double delta2;    // delta^2
+    double true_rho;  // last true |r|^2
+    double best_rho;  // best true |r|^2 so far (stagnation)
+    double m2;        // mass^2
+    int iter, iter_last_ru, ru_count, flags;
+    int stall, max_iter, ru_every, restart;  // restart: p = r after a reliable update (16-bit storage)
+};
+
+static constexpr int STALL_LIMIT = 6;
+
+__device__ __forceinline__ void fin_alpha(SolverState* st, double pq) {
+    st->pq = pq;
+    st->flags &= ~ST_XPAY_DUE;
+    if (!(pq > 0.0) || !isfinite(pq) || !isfinite(st->rho)) {
+        st->flags |= ST_BREAKDOWN | ST_DONE;
+        return;
+    }
+    st->alpha = st->rho / pq;
+}
+
+// After r -= alpha q. A reliable update is requested (the iteration's p update is then left to it) on
+// apparent convergence, when |r| fell below delta |r_true at the last update|, every ru_every iterations
+// and at the iteration cap.
+__device__ __forceinline__ void fin_update(SolverState* st, double rho_new) {
+    st->iter += 1;
+    st->rho_new = rho_new;
+    if (!isfinite(rho_new)) {
+        st->flags |= ST_BREAKDOWN | ST_DONE;
+        return;
+    }
+    const bool candidate = rho_new <= st->stop2;
+    const bool dtrig = st->delta2 > 0.0 && rho_new < st->delta2 * st->rr_ru;
+    const bool sched = st->iter - st->iter_last_ru >= st->ru_every;
+    const bool capped = st->iter >= st->max_iter;
+    if (candidate || dtrig || sched || capped) {
+        st->flags |= ST_PENDING;
+        return;
+    }
+    st->beta = rho_new / st->rho;
+    st->rho = rho_new;
+}
+
+// After a true residual r (|r|^2 = rho_true, rp = Re<r, p> with the current direction p). init = 1 for the
+// initial residual of a solve. Otherwise the paused iteration's direction update becomes
+//   p = r + beta (p - c r), beta = rho_true / rho, c = Re<r,p> / rho_true
+// which restores the orthogonality of the old direction to the new residual, or p = r (restart) when the
+// iterated vectors are stored in 16 bits.
+__device__ __forceinline__ void fin_resid(SolverState* st, double rho_true, double rp, int init) {
+    st->true_rho = rho_true;
+    if (!init) st->ru_count += 1;
+    st->iter_last_ru = st->iter;
+    st->flags &= ~ST_PENDING;
+    if (!isfinite(rho_true) || !isfinite(rp)) {
+        st->flags |= ST_BREAKDOWN | ST_DONE;
+        return;
+    }
+    if (rho_true <= st->stop2) {
+        st->flags |= ST_CONVERGED | ST_DONE;
+        return;
+    }
+    if (st->iter >= st->max_iter) {
+        st->flags |= ST_MAXIT | ST_DONE;
+        return;
+    }
+    if (init || rho_true < st->best_rho) {
+        st->best_rho = rho_true;
+        st->stall = 0;
+    } else if (++st->stall > STALL_LIMIT) {
+        st->flags |= ST_STALL | ST_DONE;
+        return;
+    }
+    st->rr_ru = rho_true;
+    if (!init) {
+        if (st->restart) {
+            st->beta = 0.0;
+            st->xpay_a = 1.0;
+        } else {
+            const double beta = rho_true / st->rho;
+            st->beta = beta;
+            st->xpay_a = 1.0 - beta * (rp / rho_true);
+        }
+        st->flags |= ST_XPAY_DUE;
+    }
+    st->rho = rho_true;
+}
+
+}  // namespace sp

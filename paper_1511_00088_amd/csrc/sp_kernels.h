@@ -1,0 +1,498 @@
+// Kernel templates of the even-odd staggered CG.
+//
+// Every solver kernel runs over a list of "groups": a group is a set of up to N systems (right-hand
+// sides) that share one gauge field and geometry. A launch covers the blocks of every group; a block
+// handles blockDim.x consecutive sites of one group for all of its systems, so the half operator loads
+// each link once per group rather than once per system. A single solve is one group with one system,
+// its descriptor passed by value (DescSingle); batches keep their descriptors in device memory
+// (DescBatch).
+//
+// Global dot products use a two-stage reduction: each block reduces its sites in FP64 (wave64 shuffles,
+// then LDS across waves) and stores one partial per system; the last block of the group to finish (an
+// atomic ticket) sums the partials in block order and updates the system's device-resident state
+// (alpha, beta, flags). Sums therefore have a fixed order and results are bitwise reproducible.
+#pragma once
+
+#include "sp_device.h"
+
+namespace sp {
+
+// Vector slots of a system.
+enum Slot : int { S_B64 = 0, S_X64, S_T64, S_XLO, S_P, S_R, S_Q, S_T, NSLOT };
+
+// Which systems a kernel works on.
+enum Gate : int {
+    G_NONE = 0,   // no state (stand-alone operator application)
+    G_ITER = 1,   // CG iteration: not done, not paused for a reliable update
+    G_RU = 2,     // reliable update requested by the last iteration (ST_PENDING)
+    G_XPAY = 3,   // the paused iteration's p update is due after the reliable update
+    G_ALIVE = 4,  // not done (set-up kernels)
+};
+
+struct SysDev {
+    void* v[NSLOT];
+    SolverState* st;
+};
+
+struct GroupDev {
+    Geom g;
+    const void* links_lo;
+    const void* links64;
+    double* partials;   // [nblk][2 N]
+    unsigned* ticket;
+    int nrhs, sys0, blk0, nblk;
+};
+
+struct DescSingle {
+    GroupDev grp;
+    SysDev sys;
+};
+
+struct DescBatch {
+    const GroupDev* grp;
+    const SysDev* sys;
+    int ngroups;
+};
+
+// --- descriptor access ---------------------------------------------------------------------------------
+__device__ __forceinline__ int find_group(const DescSingle&, int) { return 0; }
+__device__ __forceinline__ int find_group(const DescBatch& d, int lblk) {
+    int g = 0;
+    while (g + 1 < d.ngroups && lblk >= d.grp[g + 1].blk0) ++g;
+    return g;
+}
+__device__ __forceinline__ const GroupDev& grp_of(const DescSingle& d, int) { return d.grp; }
+__device__ __forceinline__ const GroupDev& grp_of(const DescBatch& d, int g) { return d.grp[g]; }
+__device__ __forceinline__ const SysDev& sys_of(const DescSingle& d, int) { return d.sys; }
+__device__ __forceinline__ const SysDev& sys_of(const DescBatch& d, int i) { return d.sys[i]; }
+
+// Block order: with remap, consecutive logical blocks (neighbouring lattice slabs) go to the same XCD.
+// The hardware hands block b to XCD b % 8; logical block = start of that XCD's contiguous range + b / 8.
+__device__ __forceinline__ int logical_block(int remap) {
+    const int b = blockIdx.x, nb = gridDim.x;
+    if (!remap) return b;
+    const int q = nb >> 3, rem = nb & 7, x = b & 7, i = b >> 3;
+    return x * q + min(x, rem) + i;
+}
+
+__device__ __forceinline__ bool gate_open(const SolverState* st, int gate) {
+    if (gate == G_NONE || st == nullptr) return true;
+    const int f = st->flags;
+    if (f & ST_DONE) return false;
+    if (gate == G_ITER) return !(f & ST_PENDING);
+    if (gate == G_RU) return (f & ST_PENDING) != 0;
+    if (gate == G_XPAY) return (f & ST_XPAY_DUE) != 0;
+    return true;
+}
+
+// Per-launch view of the systems of this block's group.
+template <int N>
+struct Rhs {
+    bool act[N];
+    SolverState* st[N];
+    bool any;
+};
+
+template <int N, class D>
+__device__ __forceinline__ Rhs<N> rhs_of(const D& d, const GroupDev& G, int gate) {
+    Rhs<N> h;
+    h.any = false;
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+        h.act[r] = false;
+        h.st[r] = nullptr;
+        if (r < G.nrhs) {
+            h.st[r] = sys_of(d, G.sys0 + r).st;
+            h.act[r] = gate_open(h.st[r], gate);
+        }
+        h.any |= h.act[r];
+    }
+    return h;
+}
+
+// Two-stage reduction of N values per thread over a group's blocks. Returns true in the last block,
+// where thread 0 then holds the group totals in v.
+template <int N>
+__device__ __forceinline__ bool group_reduce(const GroupDev& G, int gblk, double (&v)[N]) {
+    __shared__ int last;
+    block_sum<N>(v);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int r = 0; r < N; ++r) G.partials[(size_t)gblk * N + r] = v[r];
+        __threadfence();
+        const unsigned prev = atomicAdd(G.ticket, 1u);
+        last = prev == (unsigned)(G.nblk - 1);
+    }
+    __syncthreads();
+    if (!last) return false;
+    __threadfence();
+    double s[N];
+#pragma unroll
+    for (int r = 0; r < N; ++r) s[r] = 0.0;
+    for (int b = threadIdx.x; b < G.nblk; b += blockDim.x) {
+#pragma unroll
+        for (int r = 0; r < N; ++r) s[r] += G.partials[(size_t)b * N + r];
+    }
+    block_sum<N>(s);
+    if (threadIdx.x == 0) {
+        *G.ticket = 0u;
+#pragma unroll
+        for (int r = 0; r < N; ++r) v[r] = s[r];
+    }
+    return true;
+}
+
+// ------------------------------------------------------------------------------------------------------
+// Half operator, N right-hand sides sharing each link load.
+//   mode 0: out = D_{p,1-p} in
+//   mode 1: out = m^2 P - D_{p,1-p} in, block partials of Re<P, out> -> alpha = rho / Re<p, A p>
+// ------------------------------------------------------------------------------------------------------
+template <int LP, int RECON, int VP, int N, class D>
+__global__ __launch_bounds__(256) void k_dslash(D d, int p, int in_slot, int out_slot, int mode, int gate,
+                                                int use64, int remap) {
+    using R = typename Real<VP>::T;
+    using LF = LinkFmt<LP, RECON>;
+    using VF = VecFmt<VP>;
+    const int lblk = logical_block(remap);
+    const int gi = find_group(d, lblk);
+    const GroupDev& G = grp_of(d, gi);
+    const int gblk = lblk - G.blk0;
+    const Rhs<N> h = rhs_of<N>(d, G, gate);
+    if (!h.any) return;
+    const Geom g = G.g;
+    const void* links = use64 ? G.links64 : G.links_lo;
+    const void* in[N];
+    void* out[N];
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+        in[r] = h.act[r] ? sys_of(d, G.sys0 + r).v[in_slot] : nullptr;
+        out[r] = h.act[r] ? sys_of(d, G.sys0 + r).v[out_slot] : nullptr;
+    }
+    const int cb = gblk * blockDim.x + threadIdx.x;
+    double dots[N];
+#pragma unroll
+    for (int r = 0; r < N; ++r) dots[r] = 0.0;
+
+    if (cb < g.Vh) {
+        const Site s = site_of(g, p, cb);
+        Vec3<R> acc[N];
+#pragma unroll
+        for (int r = 0; r < N; ++r) acc[r] = vzero<R>();
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu) {
+            R e = (R)eta_sign(s, mu);
+            R sf = e, sb = -e;
+            if (mu == 3 && g.bc_t) {
+                if (s.t == g.T - 1) sf = -sf;
+                if (s.t == 0) sb = -sb;
+            }
+            const int nf = nbr(g, s, mu, +1);
+            const int nb = nbr(g, s, mu, -1);
+            const Su3<R> Uf = LF::load(link_block<LF>(links, g.Vh, p, mu), g.Vh, cb);
+#pragma unroll
+            for (int r = 0; r < N; ++r)
+                if (h.act[r]) mv_acc(acc[r], Uf, VF::load(in[r], g.Vh, nf), sf);
+            const Su3<R> Ub = LF::load(link_block<LF>(links, g.Vh, 1 - p, mu), g.Vh, nb);
+#pragma unroll
+            for (int r = 0; r < N; ++r)
+                if (h.act[r]) mdv_acc(acc[r], Ub, VF::load(in[r], g.Vh, nb), sb);
+        }
+#pragma unroll
+        for (int r = 0; r < N; ++r) {
+            if (!h.act[r]) continue;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                acc[r].c[i].re *= R(0.5);
+                acc[r].c[i].im *= R(0.5);
+            }
+            if (mode == 0) {
+                VF::store(out[r], g.Vh, cb, acc[r]);
+            } else {
+                const Vec3<R> pc = VF::load(sys_of(d, G.sys0 + r).v[S_P], g.Vh, cb);
+                const R m2 = (R)h.st[r]->m2;
+                Vec3<R> q;
+                double dd = 0.0;
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    q.c[i].re = m2 * pc.c[i].re - acc[r].c[i].re;
+                    q.c[i].im = m2 * pc.c[i].im - acc[r].c[i].im;
+                    dd += (double)(pc.c[i].re * q.c[i].re + pc.c[i].im * q.c[i].im);
+                }
+                dots[r] = dd;
+                VF::store(out[r], g.Vh, cb, q);
+            }
+        }
+    }
+    if (mode == 1 && group_reduce<N>(G, gblk, dots) && threadIdx.x == 0) {
+#pragma unroll
+        for (int r = 0; r < N; ++r)
+            if (h.act[r]) fin_alpha(h.st[r], dots[r]);
+    }
+}
+
+// ------------------------------------------------------------------------------------------------------
+// FP64 true residual on even sites: r = b - m^2 x + D_eo t64, t64 = D_oe x (previous launch).
+// Writes R (inner precision OP) and, when init, P = R; reduces |r|^2 and Re<r, p> -> fin_resid.
+// ------------------------------------------------------------------------------------------------------
+template <int OP, int N, class D>
+__global__ __launch_bounds__(256) void k_resid(D d, int init, int remap) {
+    using LF = LinkFmt<F64, 18>;
+    using VO = VecFmt<OP>;
+    using RO = typename Real<OP>::T;
+    const int lblk = logical_block(remap);
+    const int gi = find_group(d, lblk);
+    const GroupDev& G = grp_of(d, gi);
+    const int gblk = lblk - G.blk0;
+    const Rhs<N> h = rhs_of<N>(d, G, init ? G_ALIVE : G_RU);
+    if (!h.any) return;
+    const Geom g = G.g;
+    const int cb = gblk * blockDim.x + threadIdx.x;
+    double dots[2 * N];
+#pragma unroll
+    for (int r = 0; r < 2 * N; ++r) dots[r] = 0.0;
+    if (cb < g.Vh) {
+        const Site s = site_of(g, 0, cb);
+        Vec3<double> acc[N];
+        const void* tin[N];
+#pragma unroll
+        for (int r = 0; r < N; ++r) {
+            acc[r] = vzero<double>();
+            tin[r] = h.act[r] ? sys_of(d, G.sys0 + r).v[S_T64] : nullptr;
+        }
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu) {
+            double e = (double)eta_sign(s, mu);
+            double sf = e, sb = -e;
+            if (mu == 3 && g.bc_t) {
+                if (s.t == g.T - 1) sf = -sf;
+                if (s.t == 0) sb = -sb;
+            }
+            const int nf = nbr(g, s, mu, +1);
+            const int nb = nbr(g, s, mu, -1);
+            const Su3<double> Uf = LF::load(link_block<LF>(G.links64, g.Vh, 0, mu), g.Vh, cb);
+#pragma unroll
+            for (int r = 0; r < N; ++r)
+                if (h.act[r]) mv_acc(acc[r], Uf, VecFmt<F64>::load(tin[r], g.Vh, nf), sf);
+            const Su3<double> Ub = LF::load(link_block<LF>(G.links64, g.Vh, 1, mu), g.Vh, nb);
+#pragma unroll
+            for (int r = 0; r < N; ++r)
+                if (h.act[r]) mdv_acc(acc[r], Ub, VecFmt<F64>::load(tin[r], g.Vh, nb), sb);
+        }
+#pragma unroll
+        for (int r = 0; r < N; ++r) {
+            if (!h.act[r]) continue;
+            const SysDev& S = sys_of(d, G.sys0 + r);
+            const Vec3<double> b = VecFmt<F64>::load(S.v[S_B64], g.Vh, cb);
+            const Vec3<double> x = VecFmt<F64>::load(S.v[S_X64], g.Vh, cb);
+            const double m2 = h.st[r]->m2;
+            Vec3<RO> ro, pv;
+            if (!init) pv = VO::load(S.v[S_P], g.Vh, cb);
+            double dd = 0.0, rp = 0.0;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                const double re = b.c[i].re - m2 * x.c[i].re + 0.5 * acc[r].c[i].re;
+                const double im = b.c[i].im - m2 * x.c[i].im + 0.5 * acc[r].c[i].im;
+                dd += re * re + im * im;
+                if (!init) rp += re * (double)pv.c[i].re + im * (double)pv.c[i].im;
+                ro.c[i].re = (RO)re;
+                ro.c[i].im = (RO)im;
+            }
+            dots[2 * r] = dd;
+            dots[2 * r + 1] = rp;
+            VO::store(S.v[S_R], g.Vh, cb, ro);
+            if (init) VO::store(S.v[S_P], g.Vh, cb, ro);
+        }
+    }
+    if (group_reduce<2 * N>(G, gblk, dots) && threadIdx.x == 0) {
+#pragma unroll
+        for (int r = 0; r < N; ++r)
+            if (h.act[r]) fin_resid(h.st[r], dots[2 * r], dots[2 * r + 1], init);
+    }
+}
+
+// ------------------------------------------------------------------------------------------------------
+// x += alpha p; r -= alpha q; |r|^2 -> fin_update (beta, convergence / reliable-update triggers).
+// x is X64 (FP64) for plain FP64 CG and XLO (FP32) for the mixed solver.
+// ------------------------------------------------------------------------------------------------------
+template <int VP, int XP, int N, class D>
+__global__ __launch_bounds__(256) void k_update(D d, int remap) {
+    using R = typename Real<VP>::T;
+    using RX = typename Real<XP>::T;
+    using VF = VecFmt<VP>;
+    using XF = VecFmt<XP>;
+    const int lblk = logical_block(remap);
+    const int gi = find_group(d, lblk);
+    const GroupDev& G = grp_of(d, gi);
+    const int gblk = lblk - G.blk0;
+    const Rhs<N> h = rhs_of<N>(d, G, G_ITER);
+    if (!h.any) return;
+    const int Vh = G.g.Vh;
+    const int xslot = XP == F64 ? S_X64 : S_XLO;
+    const int cb = gblk * blockDim.x + threadIdx.x;
+    double dots[N];
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+        dots[r] = 0.0;
+        if (!h.act[r] || cb >= Vh) continue;
+        const SysDev& S = sys_of(d, G.sys0 + r);
+        const double a64 = h.st[r]->alpha;
+        const R a = (R)a64;
+        const Vec3<R> pv = VF::load(S.v[S_P], Vh, cb);
+        const Vec3<R> qv = VF::load(S.v[S_Q], Vh, cb);
+        Vec3<R> rv = VF::load(S.v[S_R], Vh, cb);
+        Vec3<RX> xv = XF::load(S.v[xslot], Vh, cb);
+        double dd = 0.0;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            xv.c[i].re += (RX)a * (RX)pv.c[i].re;
+            xv.c[i].im += (RX)a * (RX)pv.c[i].im;
+            rv.c[i].re -= a * qv.c[i].re;
+            rv.c[i].im -= a * qv.c[i].im;
+            dd += (double)(rv.c[i].re * rv.c[i].re + rv.c[i].im * rv.c[i].im);
+        }
+        dots[r] = dd;
+        XF::store(S.v[xslot], Vh, cb, xv);
+        VF::store(S.v[S_R], Vh, cb, rv);
+    }
+    if (group_reduce<N>(G, gblk, dots) && threadIdx.x == 0) {
+#pragma unroll
+        for (int r = 0; r < N; ++r)
+            if (h.act[r]) fin_update(h.st[r], dots[r]);
+    }
+}
+
+// p = r + beta p inside an iteration (gate G_ITER); p = a r + beta p after a reliable update (G_XPAY).
+template <int VP, int N, class D>
+__global__ __launch_bounds__(256) void k_xpay(D d, int gate, int remap) {
+    using R = typename Real<VP>::T;
+    using VF = VecFmt<VP>;
+    const int lblk = logical_block(remap);
+    const int gi = find_group(d, lblk);
+    const GroupDev& G = grp_of(d, gi);
+    const int gblk = lblk - G.blk0;
+    const Rhs<N> h = rhs_of<N>(d, G, gate);
+    if (!h.any) return;
+    const int Vh = G.g.Vh;
+    const int cb = gblk * blockDim.x + threadIdx.x;
+    if (cb >= Vh) return;
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+        if (!h.act[r]) continue;
+        const SysDev& S = sys_of(d, G.sys0 + r);
+        const R beta = (R)h.st[r]->beta;
+        const R a = gate == G_XPAY ? (R)h.st[r]->xpay_a : R(1);
+        const Vec3<R> rv = VF::load(S.v[S_R], Vh, cb);
+        Vec3<R> pv = VF::load(S.v[S_P], Vh, cb);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            pv.c[i].re = a * rv.c[i].re + beta * pv.c[i].re;
+            pv.c[i].im = a * rv.c[i].im + beta * pv.c[i].im;
+        }
+        VF::store(S.v[S_P], Vh, cb, pv);
+    }
+}
+
+// x64 += xlo; xlo = 0 (reliable update).
+template <int N, class D>
+__global__ __launch_bounds__(256) void k_accum(D d, int remap) {
+    const int lblk = logical_block(remap);
+    const int gi = find_group(d, lblk);
+    const GroupDev& G = grp_of(d, gi);
+    const int gblk = lblk - G.blk0;
+    const Rhs<N> h = rhs_of<N>(d, G, G_RU);
+    if (!h.any) return;
+    const int Vh = G.g.Vh;
+    const int cb = gblk * blockDim.x + threadIdx.x;
+    if (cb >= Vh) return;
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+        if (!h.act[r]) continue;
+        const SysDev& S = sys_of(d, G.sys0 + r);
+        Vec3<double> x = VecFmt<F64>::load(S.v[S_X64], Vh, cb);
+        const Vec3<float> xl = VecFmt<F32>::load(S.v[S_XLO], Vh, cb);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            x.c[i].re += (double)xl.c[i].re;
+            x.c[i].im += (double)xl.c[i].im;
+        }
+        VecFmt<F64>::store(S.v[S_X64], Vh, cb, x);
+        VecFmt<F32>::store(S.v[S_XLO], Vh, cb, vzero<float>());
+    }
+}
+
+// |b|^2 -> bnorm2 and the stopping threshold tol^2 |b|^2.
+template <int N, class D>
+__global__ __launch_bounds__(256) void k_norm_b(D d, int remap) {
+    const int lblk = logical_block(remap);
+    const int gi = find_group(d, lblk);
+    const GroupDev& G = grp_of(d, gi);
+    const int gblk = lblk - G.blk0;
+    const Rhs<N> h = rhs_of<N>(d, G, G_ALIVE);
+    if (!h.any) return;
+    const int Vh = G.g.Vh;
+    const int cb = gblk * blockDim.x + threadIdx.x;
+    double dots[N];
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+        dots[r] = 0.0;
+        if (!h.act[r] || cb >= Vh) continue;
+        const Vec3<double> b = VecFmt<F64>::load(sys_of(d, G.sys0 + r).v[S_B64], Vh, cb);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) dots[r] += b.c[i].re * b.c[i].re + b.c[i].im * b.c[i].im;
+    }
+    if (group_reduce<N>(G, gblk, dots) && threadIdx.x == 0) {
+#pragma unroll
+        for (int r = 0; r < N; ++r) {
+            if (!h.act[r]) continue;
+            h.st[r]->bnorm2 = dots[r];
+            h.st[r]->stop2 = h.st[r]->tol2 * dots[r];
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------------------------
+// Packing: natural complex128 <-> planes.
+// ------------------------------------------------------------------------------------------------------
+template <int P, int RECON>
+__global__ __launch_bounds__(256) void k_pack_gauge(Geom g, const double* __restrict__ nat, void* out) {
+    using LF = LinkFmt<P, RECON>;
+    const long V = 2L * g.Vh;
+    const long l = (long)blockIdx.x * blockDim.x + threadIdx.x;  // mu * V + lex
+    if (l >= 4 * V) return;
+    const int mu = (int)(l / V);
+    const int lex = (int)(l - (long)mu * V);
+    const int x = lex % g.X, r1 = lex / g.X, y = r1 % g.Y, r2 = r1 / g.Y, z = r2 % g.Z, t = r2 / g.Z;
+    const int q = (x + y + z + t) & 1;
+    double r[18];
+#pragma unroll
+    for (int k = 0; k < 18; ++k) r[k] = nat[l * 18 + k];
+    LF::store((void*)link_block<LF>(out, g.Vh, q, mu), g.Vh, lex >> 1, r);
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void k_pack_vec(int Vh, const double* __restrict__ nat, void* out) {
+    using R = typename Real<P>::T;
+    const int cb = blockIdx.x * blockDim.x + threadIdx.x;
+    if (cb >= Vh) return;
+    Vec3<R> v;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        v.c[c].re = (R)nat[(size_t)cb * 6 + 2 * c];
+        v.c[c].im = (R)nat[(size_t)cb * 6 + 2 * c + 1];
+    }
+    VecFmt<P>::store(out, Vh, cb, v);
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void k_unpack_vec(int Vh, const void* in, double* __restrict__ nat) {
+    const int cb = blockIdx.x * blockDim.x + threadIdx.x;
+    if (cb >= Vh) return;
+    const auto v = VecFmt<P>::load(in, Vh, cb);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        nat[(size_t)cb * 6 + 2 * c] = (double)v.c[c].re;
+        nat[(size_t)cb * 6 + 2 * c + 1] = (double)v.c[c].im;
+    }
+}
+
+}  // namespace sp

@@ -1,0 +1,105 @@
+"""GPU parity of the half staggered operator (sp_dslash through the C-ABI) against the FP64 oracle.
+
+Small lattices are compared element by element; lattice volumes are chosen so that the last block of the
+launch is ragged. The 20^3x64 workload (the benchmark's) is compared on sampled sites that the oracle
+evaluates one by one, with the tuned launch the benchmark uses.
+"""
+import numpy as np
+import pytest
+import torch
+
+import lattice_inputs as li
+import oracle
+import paper_1511_00088_amd as sp
+from conftest import rel_err_max
+from gpu_common import DSLASH_TOL, announce, gauge, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+COMBOS = [("f64", 18), ("f32", 18), ("f32", 12), ("f16", 18), ("f16", 12), ("bf16", 18), ("bf16", 12)]
+
+
+@pytest.mark.parametrize("prec,recon", COMBOS)
+@pytest.mark.parametrize("dims,bc_t", [((4, 4, 4, 4), 0), ((8, 6, 4, 10), 1), ((2, 2, 2, 2), 0)])
+def test_dslash_parity_small(prec, recon, dims, bc_t):
+    announce(f"dslash {prec} r{recon} dims={dims} bc_t={bc_t}")
+    V = li.volume(dims)
+    U = li.haar_links(dims, 101) if dims != (8, 6, 4, 10) else li.near_identity_links(dims, 0.3, 102)
+    G = gauge(dims, U, prec if prec != "f64" else "f64", recon, bc_t)
+    for p in (0, 1):
+        xin = li.gaussian_vector(V // 2, 103 + p)
+        y = to_host(sp.dslash(G, to_dev(xin), p, prec))
+        ref = oracle.dslash_eo(dims, U, xin, p, bc_t=bc_t)
+        err = rel_err_max(y, ref)
+        announce(f"  parity {p}: max rel err {err:.3e}")
+        assert err <= DSLASH_TOL[prec], (prec, recon, p, err)
+
+
+@pytest.mark.parametrize("prec,recon", COMBOS)
+def test_dslash_parity_cfg1_sampled(prec, recon):
+    """20^3x64 near-identity links: sampled sites (random + the ragged tail + the lattice corners)."""
+    dims = (20, 20, 20, 64)
+    announce(f"dslash cfg1 sampled {prec} r{recon}")
+    U = _cfg1_links()
+    V = li.volume(dims)
+    G = gauge(dims, U, prec, recon)
+    sp.tune_dslash(G, prec)
+    xin = li.gaussian_vector(V // 2, 104)
+    rng = np.random.default_rng(105)
+    cbs = np.unique(np.concatenate([rng.integers(0, V // 2, 3000), np.arange(V // 2 - 300, V // 2),
+                                    np.arange(0, 300)]))
+    for p in (0, 1):
+        y = to_host(sp.dslash(G, to_dev(xin), p, prec))[cbs]
+        ref = oracle.dslash_eo_sites(dims, U, xin, p, cbs)
+        err = rel_err_max(y, ref)
+        announce(f"  parity {p}: sampled max rel err {err:.3e}")
+        assert err <= DSLASH_TOL[prec]
+
+
+_CACHE = {}
+
+
+def _cfg1_links():
+    if "U" not in _CACHE:
+        _CACHE["U"] = li.near_identity_links((20, 20, 20, 64), 0.3, 21)
+    return _CACHE["U"]
+
+
+def test_pack_roundtrip():
+    dims = (4, 6, 4, 8)
+    V = li.volume(dims)
+    lat = sp.Lattice(dims)
+    v = li.gaussian_vector(V // 2, 106)
+    for prec, tol in (("f64", 0.0), ("f32", 1e-7), ("f16", 1e-3), ("bf16", 8e-3)):
+        back = to_host(sp.unpack_vec(lat, sp.pack_vec(lat, to_dev(v), prec), prec))
+        err = rel_err_max(back, v)
+        assert err <= tol, (prec, err)
+
+
+def test_dslash_deterministic():
+    dims = (8, 8, 8, 8)
+    V = li.volume(dims)
+    U = li.haar_links(dims, 107)
+    G = gauge(dims, U, "f32")
+    lat = G.lat
+    xin = sp.pack_vec(lat, to_dev(li.gaussian_vector(V // 2, 108)), "f32")
+    a = sp.dslash_packed(G, "f32", xin, 1).clone()
+    b = sp.dslash_packed(G, "f32", xin, 1).clone()
+    assert torch.equal(a, b)
+
+
+def test_dslash_argument_errors():
+    dims = (4, 4, 4, 4)
+    G = gauge(dims, li.haar_links(dims, 109), "f32")
+    lat = G.lat
+    v = torch.zeros(lat.vec_bytes("f32"), dtype=torch.uint8, device="cuda:0")
+    with pytest.raises(sp.StagError) as e:
+        sp.dslash_packed(G, "f32", v, 2)
+    assert e.value.code == -1
+    with pytest.raises(sp.StagError) as e:
+        sp.dslash_packed(G, "f16", v, 1)  # the gauge field carries an FP32 packing only
+    assert e.value.code == -3
+    odd = sp.Lattice((4, 4, 5, 4))
+    with pytest.raises(sp.StagError) as e:
+        sp.pack_vec(odd, torch.zeros((odd.Vh, 3), dtype=torch.complex128, device="cuda:0"), "f32")
+    assert e.value.code == -2
