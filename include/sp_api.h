@@ -71,16 +71,22 @@ typedef struct {
 } sp_gauge;
 
 /* Solver parameters.
- *  tol        stop when the FP64 true residual |b - A x| / |b| <= tol (> 0)
+ *  tol        stop when the FP64 true residual |b - A x| / |b| <= tol (> 0, < 1)
  *  max_iter   iteration cap (> 0)
  *  inner      precision of the iterated vectors and links: SP_F64 gives plain FP64 CG; SP_F32, SP_F16,
- *             SP_BF16 give mixed precision with FP64 reliable updates
- *  delta      extra reliable update when |r_iterated| < delta * |r at the last update| (0 disables)
- *  ru_every   reliable update at least every ru_every iterations (ignored for SP_F64; <= 0 picks 100
- *             for SP_F32 and 50 for 16-bit storage)
- *  poll_chunk iterations per device-side chunk between host convergence polls (<= 0 picks 50)
+ *             SP_BF16 give mixed precision with FP64 reliable updates (true residual recomputed from an
+ *             FP64 solution that accumulates the low-precision increments)
+ *  delta      reliable update when |r_iterated| < delta * |r at the last update| (0 disables; checked at
+ *             the end of each poll chunk)
+ *  ru_every   reliable update at least every ru_every iterations (ignored for SP_F64; <= 0 picks 100;
+ *             checked at the end of each poll chunk)
+ *  poll_chunk iterations per device-side chunk (one hipGraph launch) between host convergence polls
+ *             (<= 0 picks 25)
  *  use_x0     1: x_e holds the initial guess on entry; 0: start from zero
- *  use_graph  1: capture each chunk in a hipGraph and replay it; 0: launch kernels one by one */
+ *  use_graph  1: capture each chunk in a hipGraph and replay it; 0: launch kernels one by one
+ * A reliable update also runs whenever the iterated residual reaches tol and at the iteration cap. After
+ * it, FP32 iterations keep the search direction (re-orthogonalised against the new residual); 16-bit
+ * storage restarts it from the residual. */
 typedef struct {
     double tol;
     int32_t max_iter;

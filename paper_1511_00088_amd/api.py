@@ -146,7 +146,7 @@ _default_ws = Workspace()
 
 
 def cg_solve(gauge: Gauge, mass: float, b: torch.Tensor, tol: float = 1e-8, inner="f32", max_iter: int = 100000,
-             delta: float = 0.1, ru_every: int = 0, poll_chunk: int = 50, x0: torch.Tensor | None = None,
+             delta: float = 0.1, ru_every: int = 0, poll_chunk: int = 0, x0: torch.Tensor | None = None,
              use_graph: bool = True, workspace: Workspace | None = None, out: torch.Tensor | None = None,
              raise_on_not_converged: bool = False):
     """Solve (m^2 - D_eo D_oe) x = b on even sites. Returns (x, SolveStats)."""
@@ -175,7 +175,7 @@ def cg_solve(gauge: Gauge, mass: float, b: torch.Tensor, tol: float = 1e-8, inne
 
 
 def cg_solve_batched(systems, tol: float = 1e-8, inner="f32", max_iter: int = 100000, delta: float = 0.1,
-                     ru_every: int = 0, poll_chunk: int = 50, use_graph: bool = True,
+                     ru_every: int = 0, poll_chunk: int = 0, use_graph: bool = True,
                      workspace: Workspace | None = None):
     """Solve many systems together. systems: list of (Gauge, mass, b). Returns (list of x, list of stats)."""
     n = len(systems)

@@ -159,21 +159,21 @@ struct GroupPlan {
     const sp_gauge* U;
     std::vector<int> sys;  // indices into the caller's system list
     int nblk = 0, blk0 = 0;
-    size_t partials_off = 0;
+    size_t partials_off = 0, partials_p_off = 0;
 };
 
 struct Layout {
     std::vector<GroupPlan> groups;
     std::vector<size_t> sys_off;  // byte offset of each system's vector block
     std::vector<int> sys_group;
-    size_t states_off = 0, tickets_off = 0, gdesc_off = 0, sdesc_off = 0, ctrl_bytes = 0;
+    size_t states_off = 0, gdesc_off = 0, sdesc_off = 0, ctrl_bytes = 0;
     size_t total = 0;
     int inner = SP_F32, nbatch_rhs = 1;
     int total_blocks = 0;
     LaunchCfg cfg;
 };
 
-// Per-system vector block: B64 X64 T64 (48 B/site), XLO (24 B/site, mixed only), P R Q T (inner).
+// Per-system vector block: B64 X64 T64 (48 B/site), XLO (24 B/site, mixed only), P R T (inner).
 size_t sys_block_bytes(int Vh, int inner, size_t slot_off[NSLOT]) {
     size_t off = 0;
     const size_t v64 = align256((size_t)Vh * 48);
@@ -184,7 +184,6 @@ size_t sys_block_bytes(int Vh, int inner, size_t slot_off[NSLOT]) {
     slot_off[S_XLO] = off; if (inner != SP_F64) off += align256((size_t)Vh * 24);
     slot_off[S_P] = off; off += vin;
     slot_off[S_R] = off; off += vin;
-    slot_off[S_Q] = off; off += vin;
     slot_off[S_T] = off; off += vin;
     return off;
 }
@@ -240,12 +239,10 @@ int make_layout(int nsys, const sp_system* systems, const sp_cg_params* prm, int
         blk += G.nblk;
     }
     L->total_blocks = blk;
-    // control block: states, tickets, descriptors
+    // control block: states, descriptors
     size_t off = 0;
     L->states_off = off;
     off += align256(sizeof(SolverState) * nsys);
-    L->tickets_off = off;
-    off += align256(64 * L->groups.size());
     L->gdesc_off = off;
     off += align256(sizeof(GroupDev) * L->groups.size());
     L->sdesc_off = off;
@@ -255,6 +252,8 @@ int make_layout(int nsys, const sp_system* systems, const sp_cg_params* prm, int
     for (auto& G : L->groups) {
         G.partials_off = off;
         off += align256(sizeof(double) * (size_t)(2 * NB) * blocks_for(G.g.Vh, 64));
+        G.partials_p_off = off;
+        off += align256(sizeof(double) * (size_t)NB * blocks_for(G.g.Vh, 64));
     }
     L->sys_off.assign(nsys, 0);
     L->sys_group.assign(nsys, 0);
@@ -283,40 +282,54 @@ int check_gauge(const sp_gauge* U, int inner) {
 // Enqueue helpers
 // ---------------------------------------------------------------------------------------------------
 struct Plan {
-    int inner, lp, recon, nblocks;
+    int inner, lp, recon, nblocks, ngroups;
     LaunchCfg cfg;
 };
 
+// One CG iteration: t = D_oe p (|t|^2) -> alpha -> x += alpha p, r -= alpha (m^2 p - D_eo t) (|r|^2) -> beta
+// and triggers -> p = r + beta p (|p|^2).
 template <class D>
 hipError_t enqueue_iterations(const D& d, const Plan& pl, int count, hipStream_t s) {
     const int use64 = pl.inner == SP_F64;
     for (int i = 0; i < count; ++i) {
         hipError_t e;
-        if ((e = launch_dslash(d, pl.nblocks, pl.cfg, pl.lp, pl.recon, pl.inner, 1, S_P, S_T, 0, G_ITER, use64, s)))
+        if ((e = launch_dslash(d, pl.nblocks, pl.cfg, pl.lp, pl.recon, pl.inner, 1, S_P, S_T, DS_NORM, G_ITER, use64,
+                               s)))
             return e;
-        if ((e = launch_dslash(d, pl.nblocks, pl.cfg, pl.lp, pl.recon, pl.inner, 0, S_T, S_Q, 1, G_ITER, use64, s)))
+        if ((e = launch_finalize(d, pl.ngroups, FIN_ALPHA, G_ITER, s))) return e;
+        if ((e = launch_dslash(d, pl.nblocks, pl.cfg, pl.lp, pl.recon, pl.inner, 0, S_T, S_R, DS_UPDATE, G_ITER,
+                               use64, s)))
             return e;
-        if ((e = launch_update(d, pl.nblocks, pl.cfg, pl.inner, s))) return e;
+        if ((e = launch_finalize(d, pl.ngroups, i + 1 == count ? FIN_UPDATE_END : FIN_UPDATE, G_ITER, s))) return e;
         if ((e = launch_xpay(d, pl.nblocks, pl.cfg, pl.inner, G_ITER, s))) return e;
     }
     return hipSuccess;
 }
 
+// Reliable update (runs only for systems whose last iteration requested it): x64 += x_lo; t64 = D_oe x64;
+// r = b - A x64 in FP64 (|r|^2, Re<r,p>) -> state; p = a r + beta p.
 template <class D>
 hipError_t enqueue_reliable(const D& d, const Plan& pl, hipStream_t s) {
     hipError_t e;
     if (pl.inner != SP_F64 && (e = launch_accum(d, pl.nblocks, pl.cfg, s))) return e;
-    if ((e = launch_dslash(d, pl.nblocks, pl.cfg, SP_F64, 18, SP_F64, 1, S_X64, S_T64, 0, G_RU, 1, s))) return e;
+    if ((e = launch_dslash(d, pl.nblocks, pl.cfg, SP_F64, 18, SP_F64, 1, S_X64, S_T64, DS_PLAIN, G_RU, 1, s)))
+        return e;
     if ((e = launch_resid(d, pl.nblocks, pl.cfg, pl.inner, 0, s))) return e;
+    if ((e = launch_finalize(d, pl.ngroups, FIN_RESID, G_RU, s))) return e;
     return launch_xpay(d, pl.nblocks, pl.cfg, pl.inner, G_XPAY, s);
 }
 
+// Start of a solve: |b|^2; r = b - A x0 in FP64; p = r.
 template <class D>
 hipError_t enqueue_setup(const D& d, const Plan& pl, hipStream_t s) {
     hipError_t e;
     if ((e = launch_norm_b(d, pl.nblocks, pl.cfg, s))) return e;
-    if ((e = launch_dslash(d, pl.nblocks, pl.cfg, SP_F64, 18, SP_F64, 1, S_X64, S_T64, 0, G_ALIVE, 1, s))) return e;
-    return launch_resid(d, pl.nblocks, pl.cfg, pl.inner, 1, s);
+    if ((e = launch_finalize(d, pl.ngroups, FIN_NORM_B, G_ALIVE, s))) return e;
+    if ((e = launch_dslash(d, pl.nblocks, pl.cfg, SP_F64, 18, SP_F64, 1, S_X64, S_T64, DS_PLAIN, G_ALIVE, 1, s)))
+        return e;
+    if ((e = launch_resid(d, pl.nblocks, pl.cfg, pl.inner, 1, s))) return e;
+    if ((e = launch_finalize(d, pl.ngroups, FIN_RESID_INIT, G_ALIVE, s))) return e;
+    return launch_xpay(d, pl.nblocks, pl.cfg, pl.inner, G_XPAY, s);
 }
 
 template <class D>
@@ -433,6 +446,9 @@ int solve_impl(int nsys, const sp_system* systems, const sp_cg_params* prm, sp_c
     if (ws_bytes < L.total) return fail(SP_ERR_WORKSPACE, "workspace %zu bytes < required %zu", ws_bytes, L.total);
     if (((uintptr_t)ws) & 255) return fail(SP_ERR_INVALID_ARG, "workspace not 256-byte aligned");
     char* base = (char*)ws;
+    for (auto& G : L.groups)
+        if ((L.inner != SP_F64) && (G.U->recon != L.groups[0].U->recon || G.U->lo_prec != L.groups[0].U->lo_prec))
+            return fail(SP_ERR_UNSUPPORTED, "all systems of a batch must share the link packing");
 
     // ---- control block on the host ----
     HIP_TRY(g_upload.ensure(L.ctrl_bytes));
@@ -452,7 +468,7 @@ int solve_impl(int nsys, const sp_system* systems, const sp_cg_params* prm, sp_c
         gd.links64 = G.U->f64;
         gd.links_lo = prm->inner == SP_F64 ? G.U->f64 : G.U->lo;
         gd.partials = (double*)(base + G.partials_off);
-        gd.ticket = (unsigned*)(base + L.tickets_off + 64 * k);
+        gd.partials_p = (double*)(base + G.partials_p_off);
         gd.nrhs = (int)G.sys.size();
         gd.sys0 = sys_counter;
         gd.blk0 = G.blk0;
@@ -488,12 +504,10 @@ int solve_impl(int nsys, const sp_system* systems, const sp_cg_params* prm, sp_c
     pl.lp = L.inner == SP_F64 ? SP_F64 : L.groups[0].U->lo_prec;
     pl.recon = L.inner == SP_F64 ? 18 : L.groups[0].U->recon;
     pl.nblocks = L.total_blocks;
+    pl.ngroups = (int)L.groups.size();
     pl.cfg = L.cfg;
-    for (auto& G : L.groups)
-        if ((L.inner != SP_F64) && (G.U->recon != pl.recon || G.U->lo_prec != pl.lp))
-            return fail(SP_ERR_UNSUPPORTED, "all systems of a batch must share the link packing");
 
-    const int chunk = prm->poll_chunk > 0 ? prm->poll_chunk : 20;
+    const int chunk = prm->poll_chunk > 0 ? prm->poll_chunk : 25;
     HIP_TRY(g_poll.ensure(2 * sizeof(SolverState) * nsys));
     SolverState* slots[2] = {(SolverState*)g_poll.p, (SolverState*)g_poll.p + nsys};
 
@@ -520,29 +534,61 @@ int solve_impl(int nsys, const sp_system* systems, const sp_cg_params* prm, sp_c
     Events ev;
     HIP_TRY(ev.create());
     // Chunks are pipelined: chunk c is queued before the state written by chunk c-1 is inspected, so the
-    // GPU never waits for the host. Once every system is done, the chunk queued meanwhile finds all
-    // systems stopped and its kernels return at entry.
+    // GPU does not wait for the host. Near convergence (estimated from the residual decay between polls)
+    // the host waits for each chunk before queueing the next one, so that no chunk is launched only to
+    // find every system stopped.
     const long max_chunks = (long)prm->max_iter / chunk + 64;
     SolverState* poll = nullptr;
+    std::vector<double> last_rho(nsys, -1.0);
+    std::vector<int> last_iter(nsys, 0);
+    bool careful = false;
+    auto all_done = [&](const SolverState* st) {
+        for (int i = 0; i < nsys; ++i)
+            if (!(st[i].flags & ST_DONE)) return false;
+        return true;
+    };
     for (long c = 0;; ++c) {
+        if (careful && c > 0) {
+            HIP_TRY(hipEventSynchronize(ev.e[(c - 1) & 1]));
+            if (all_done(slots[(c - 1) & 1])) {
+                poll = slots[(c - 1) & 1];
+                break;
+            }
+        }
         if (exec) HIP_TRY(hipGraphLaunch(exec, stream));
         else HIP_TRY(batched ? enqueue_chunk(db, pl, chunk, stream) : enqueue_chunk(ds, pl, chunk, stream));
         HIP_TRY(hipMemcpyAsync(slots[c & 1], base + L.states_off, sizeof(SolverState) * nsys, hipMemcpyDeviceToHost,
                                stream));
         HIP_TRY(hipEventRecord(ev.e[c & 1], stream));
-        if (c == 0) continue;
+        if (c > max_chunks) {
+            // cannot happen unless the device state is corrupted: every system stops at max_iter
+            HIP_TRY(hipStreamSynchronize(stream));
+            return fail(SP_ERR_HIP, "solver did not stop after %ld chunks", c);
+        }
+        if (careful || c == 0) continue;
         HIP_TRY(hipEventSynchronize(ev.e[(c - 1) & 1]));
         SolverState* prev = slots[(c - 1) & 1];
-        bool all_done = true;
-        for (int i = 0; i < nsys; ++i) all_done &= (prev[i].flags & ST_DONE) != 0;
-        if (all_done) {
+        if (all_done(prev)) {
             poll = prev;
             break;
         }
-        if (c > max_chunks) {
-            // cannot happen unless the device state is corrupted: every system stops at max_iter
-            return fail(SP_ERR_HIP, "solver did not stop after %ld chunks", c);
+        // iterations still needed, from the decay of the iterated |r|^2 since the previous poll
+        double need = 0.0;
+        for (int i = 0; i < nsys; ++i) {
+            const SolverState& st = prev[i];
+            if (st.flags & ST_DONE) continue;
+            const double rho = st.rho_new > 0 ? st.rho_new : st.rho;
+            double est = 1e30;
+            if (last_rho[i] > 0 && rho > 0 && rho < last_rho[i] && st.iter > last_iter[i] && st.stop2 > 0) {
+                const double rate = std::log(last_rho[i] / rho) / (st.iter - last_iter[i]);
+                est = rho <= st.stop2 ? 0.0 : std::log(rho / st.stop2) / rate;
+            }
+            need = std::max(need, est);
+            last_rho[i] = rho;
+            last_iter[i] = st.iter;
         }
+        // chunk c is in flight: switch when what is left fits in it and the next one
+        careful = need <= 1.5 * chunk;
     }
 
     // ---- unpack x ----
@@ -687,7 +733,7 @@ int sp_dslash(const sp_geom* g, const sp_gauge* U, int prec, const void* in, voi
     }
     const int nb = blocks_for(G.Vh, c.nt);
     d.grp.nblk = nb;
-    HIP_TRY(launch_dslash(d, nb, c, lp, recon, prec, out_parity, S_P, S_T, 0, G_NONE, prec == SP_F64,
+    HIP_TRY(launch_dslash(d, nb, c, lp, recon, prec, out_parity, S_P, S_T, DS_PLAIN, G_NONE, prec == SP_F64,
                           (hipStream_t)stream));
     return SP_OK;
 }
@@ -714,10 +760,10 @@ int sp_tune_dslash(const sp_geom* g, const sp_gauge* U, int prec, void* in, void
             const int nb = blocks_for(G.Vh, nt);
             d.grp.nblk = nb;
             for (int w = 0; w < 3; ++w)
-                HIP_TRY(launch_dslash(d, nb, c, lp, recon, prec, 1, S_P, S_T, 0, G_NONE, prec == SP_F64, s));
+                HIP_TRY(launch_dslash(d, nb, c, lp, recon, prec, 1, S_P, S_T, DS_PLAIN, G_NONE, prec == SP_F64, s));
             HIP_TRY(hipEventRecord(e0, s));
             for (int k = 0; k < reps; ++k)
-                HIP_TRY(launch_dslash(d, nb, c, lp, recon, prec, 1, S_P, S_T, 0, G_NONE, prec == SP_F64, s));
+                HIP_TRY(launch_dslash(d, nb, c, lp, recon, prec, 1, S_P, S_T, DS_PLAIN, G_NONE, prec == SP_F64, s));
             HIP_TRY(hipEventRecord(e1, s));
             HIP_TRY(hipEventSynchronize(e1));
             float ms = 0;
@@ -816,7 +862,7 @@ int sp_cg_solve_batched(int nsys, const sp_system* systems, const sp_cg_params* 
 size_t sp_force_workspace_bytes(const sp_geom* g) {
     Geom G;
     if (check_geom(g, &G)) return 0;
-    return 4 * align256((size_t)G.Vh * 48) + align256(sizeof(double) * (size_t)mass_grad_blocks(G)) + 256;
+    return 4 * align256((size_t)G.Vh * 48) + align256(sizeof(double) * (size_t)mass_grad_blocks(G));
 }
 
 int sp_cg_force(const sp_geom* g, const sp_gauge* U, double mass, const double* x_e, const double* lambda_e,
@@ -837,10 +883,8 @@ int sp_cg_force(const sp_geom* g, const sp_gauge* U, double mass, const double* 
     void* yx = base + 2 * v;
     void* yl = base + 3 * v;
     double* partials = (double*)(base + 4 * v);
-    unsigned* ticket = (unsigned*)(base + 4 * v + align256(sizeof(double) * (size_t)mass_grad_blocks(G)));
     HIP_TRY(launch_pack_vec(G.Vh, x_e, SP_F64, xp, s));
     HIP_TRY(launch_pack_vec(G.Vh, lambda_e, SP_F64, lp, s));
-    HIP_TRY(launch_zero(ticket, 256, s));
     sp_gauge Ug = *U;
     Ug.lo = U->f64;
     Ug.lo_prec = SP_F64;
@@ -849,7 +893,7 @@ int sp_cg_force(const sp_geom* g, const sp_gauge* U, double mass, const double* 
     rc = sp_dslash(g, &Ug, SP_F64, lp, yl, 1, stream);
     if (rc) return rc;
     HIP_TRY(launch_force(G, U->f64, xp, lp, yx, yl, gamma, force, s));
-    if (grad_mass) HIP_TRY(launch_mass_grad(G, mass, xp, lp, partials, ticket, grad_mass, s));
+    if (grad_mass) HIP_TRY(launch_mass_grad(G, mass, xp, lp, partials, grad_mass, s));
     HIP_TRY(hipStreamSynchronize(s));
     return SP_OK;
 }

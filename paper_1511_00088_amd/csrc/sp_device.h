@@ -159,6 +159,11 @@ struct VecFmt<F64> {
 #pragma unroll
         for (int c = 0; c < 3; ++c) p[(size_t)c * Vh + cb] = make_double2(v.c[c].re, v.c[c].im);
     }
+    // store and return the value as stored
+    __device__ static Vec3<double> store_rt(void* base, int Vh, int cb, const Vec3<double>& v) {
+        store(base, Vh, cb, v);
+        return v;
+    }
 };
 
 template <>
@@ -180,6 +185,10 @@ struct VecFmt<F32> {
         p4[cb] = make_float4(v.c[0].re, v.c[0].im, v.c[1].re, v.c[1].im);
         p2[cb] = make_float2(v.c[2].re, v.c[2].im);
     }
+    __device__ static Vec3<float> store_rt(void* base, int Vh, int cb, const Vec3<float>& v) {
+        store(base, Vh, cb, v);
+        return v;
+    }
 };
 
 template <int P>
@@ -199,19 +208,29 @@ struct VecFmt16 {
         v.c[2].re = s * unpack_lo<P>(b);   v.c[2].im = s * unpack_hi<P>(b);
         return v;
     }
-    __device__ static void store(void* base, int Vh, int cb, const Vec3<float>& v) {
+    __device__ static void store(void* base, int Vh, int cb, const Vec3<float>& v) { (void)store_rt(base, Vh, cb, v); }
+    // store and return the value as stored (rounded to 16 bits, scaled by the site norm)
+    __device__ static Vec3<float> store_rt(void* base, int Vh, int cb, const Vec3<float>& v) {
         uint2* pa = (uint2*)base;
         uint32_t* pb = (uint32_t*)(pa + Vh);
-        float inv = 1.0f;
+        float inv = 1.0f, m = 1.0f;
         if constexpr (scaled) {
-            float m = 0.0f;
+            m = 0.0f;
 #pragma unroll
             for (int c = 0; c < 3; ++c) m = fmaxf(m, fmaxf(fabsf(v.c[c].re), fabsf(v.c[c].im)));
             ((float*)(pb + Vh))[cb] = m;
             inv = m > 0.0f ? 1.0f / m : 0.0f;
         }
-        pa[cb] = make_uint2(pack2<P>(inv * v.c[0].re, inv * v.c[0].im), pack2<P>(inv * v.c[1].re, inv * v.c[1].im));
-        pb[cb] = pack2<P>(inv * v.c[2].re, inv * v.c[2].im);
+        const uint32_t w0 = pack2<P>(inv * v.c[0].re, inv * v.c[0].im);
+        const uint32_t w1 = pack2<P>(inv * v.c[1].re, inv * v.c[1].im);
+        const uint32_t w2 = pack2<P>(inv * v.c[2].re, inv * v.c[2].im);
+        pa[cb] = make_uint2(w0, w1);
+        pb[cb] = w2;
+        Vec3<float> o;
+        o.c[0].re = m * unpack_lo<P>(w0); o.c[0].im = m * unpack_hi<P>(w0);
+        o.c[1].re = m * unpack_lo<P>(w1); o.c[1].im = m * unpack_hi<P>(w1);
+        o.c[2].re = m * unpack_lo<P>(w2); o.c[2].im = m * unpack_hi<P>(w2);
+        return o;
     }
 };
 template <>
@@ -485,7 +504,7 @@ enum : int {
     ST_MAXIT = 8,       // iteration cap reached
     ST_STALL = 16,      // true residual stopped improving
     ST_CONVERGED = 32,  // true residual <= tol |b|
-    ST_XPAY_DUE = 64,   // the paused iteration's p = r + beta p is still to be done
+    ST_XPAY_DUE = 64,   // p = a r + beta p is due (after a reliable update, or p = r at the start)
 };
 
 struct alignas(64) SolverState {
@@ -517,20 +536,22 @@ __device__ __forceinline__ void fin_alpha(SolverState* st, double pq) {
 }
 
 // After r -= alpha q. A reliable update is requested (the iteration's p update is then left to it) on
-// apparent convergence, when |r| fell below delta |r_true at the last update|, every ru_every iterations
-// and at the iteration cap.
-__device__ __forceinline__ void fin_update(SolverState* st, double rho_new) {
+// apparent convergence and at the iteration cap at any iteration; on the last iteration of a chunk also
+// when |r| fell below delta |r_true at the last update| or ru_every iterations have passed. Keeping the
+// last two triggers at chunk ends means a chunk never stops early for them.
+__device__ __forceinline__ void fin_update(SolverState* st, double rho_new, bool chunk_end) {
     st->iter += 1;
     st->rho_new = rho_new;
     if (!isfinite(rho_new)) {
         st->flags |= ST_BREAKDOWN | ST_DONE;
         return;
     }
-    const bool candidate = rho_new <= st->stop2;
-    const bool dtrig = st->delta2 > 0.0 && rho_new < st->delta2 * st->rr_ru;
-    const bool sched = st->iter - st->iter_last_ru >= st->ru_every;
-    const bool capped = st->iter >= st->max_iter;
-    if (candidate || dtrig || sched || capped) {
+    bool pause = rho_new <= st->stop2 || st->iter >= st->max_iter;
+    if (chunk_end) {
+        pause |= st->delta2 > 0.0 && rho_new < st->delta2 * st->rr_ru;
+        pause |= st->iter - st->iter_last_ru >= st->ru_every;
+    }
+    if (pause) {
         st->flags |= ST_PENDING;
         return;
     }
@@ -539,7 +560,8 @@ __device__ __forceinline__ void fin_update(SolverState* st, double rho_new) {
 }
 
 // After a true residual r (|r|^2 = rho_true, rp = Re<r, p> with the current direction p). init = 1 for the
-// initial residual of a solve. Otherwise the paused iteration's direction update becomes
+// initial residual of a solve, which is followed by p = r. Otherwise the paused iteration's direction
+// update becomes
 //   p = r + beta (p - c r), beta = rho_true / rho, c = Re<r,p> / rho_true
 // which restores the orthogonality of the old direction to the new residual, or p = r (restart) when the
 // iterated vectors are stored in 16 bits.
@@ -568,7 +590,10 @@ __device__ __forceinline__ void fin_resid(SolverState* st, double rho_true, doub
         return;
     }
     st->rr_ru = rho_true;
-    if (!init) {
+    if (init) {
+        st->beta = 0.0;  // p = r
+        st->xpay_a = 1.0;
+    } else {
         if (st->restart) {
             st->beta = 0.0;
             st->xpay_a = 1.0;
@@ -577,8 +602,8 @@ __device__ __forceinline__ void fin_resid(SolverState* st, double rho_true, doub
             st->beta = beta;
             st->xpay_a = 1.0 - beta * (rp / rho_true);
         }
-        st->flags |= ST_XPAY_DUE;
     }
+    st->flags |= ST_XPAY_DUE;
     st->rho = rho_true;
 }
 

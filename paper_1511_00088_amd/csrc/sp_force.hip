@@ -89,8 +89,8 @@ __global__ __launch_bounds__(256) void k_force(Geom g, const void* links64, cons
     }
 }
 
-__global__ __launch_bounds__(256) void k_mass_grad(int Vh, double mass, const void* x, const void* lam,
-                                                   double* partials, unsigned* ticket, double* out) {
+__global__ __launch_bounds__(256) void k_mass_grad_partials(int Vh, const void* x, const void* lam,
+                                                            double* partials) {
     using VF = VecFmt<F64>;
     const int cb = blockIdx.x * blockDim.x + threadIdx.x;
     double v[1] = {0.0};
@@ -100,23 +100,17 @@ __global__ __launch_bounds__(256) void k_mass_grad(int Vh, double mass, const vo
 #pragma unroll
         for (int i = 0; i < 3; ++i) v[0] += a.c[i].re * b.c[i].re + a.c[i].im * b.c[i].im;
     }
-    __shared__ int last;
     block_sum<1>(v);
-    if (threadIdx.x == 0) {
-        partials[blockIdx.x] = v[0];
-        __threadfence();
-        last = atomicAdd(ticket, 1u) == gridDim.x - 1;
-    }
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
+    if (threadIdx.x == 0) partials[blockIdx.x] = v[0];
+}
+
+// out = -2 m sum(partials), summed in block order by one block.
+__global__ __launch_bounds__(256) void k_mass_grad_final(int nblk, double mass, const double* partials,
+                                                         double* out) {
     double s[1] = {0.0};
-    for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x) s[0] += partials[b];
+    for (int b = threadIdx.x; b < nblk; b += blockDim.x) s[0] += partials[b];
     block_sum<1>(s);
-    if (threadIdx.x == 0) {
-        *ticket = 0u;
-        *out = -2.0 * mass * s[0];
-    }
+    if (threadIdx.x == 0) *out = -2.0 * mass * s[0];
 }
 
 int mass_grad_blocks(const Geom& g) { return blocks_for(g.Vh, 256); }
@@ -130,9 +124,12 @@ hipError_t launch_force(const Geom& g, const void* links64, const void* x, const
 }
 
 hipError_t launch_mass_grad(const Geom& g, double mass, const void* x, const void* lam, double* partials,
-                            unsigned* ticket, double* out, hipStream_t s) {
-    hipLaunchKernelGGL(k_mass_grad, dim3(mass_grad_blocks(g)), dim3(256), 0, s, g.Vh, mass, x, lam, partials,
-                       ticket, out);
+                            double* out, hipStream_t s) {
+    const int nb = mass_grad_blocks(g);
+    hipLaunchKernelGGL(k_mass_grad_partials, dim3(nb), dim3(256), 0, s, g.Vh, x, lam, partials);
+    hipError_t e = hipGetLastError();
+    if (e) return e;
+    hipLaunchKernelGGL(k_mass_grad_final, dim3(1), dim3(256), 0, s, nb, mass, partials, out);
     return hipGetLastError();
 }
 

@@ -8,9 +8,10 @@
 // (DescBatch).
 //
 // Global dot products use a two-stage reduction: each block reduces its sites in FP64 (wave64 shuffles,
-// then LDS across waves) and stores one partial per system; the last block of the group to finish (an
-// atomic ticket) sums the partials in block order and updates the system's device-resident state
-// (alpha, beta, flags). Sums therefore have a fixed order and results are bitwise reproducible.
+// then LDS across waves) and stores one partial per system; the next launch, k_finalize (one block per
+// group), sums the partials in block order and updates each system's device-resident state (alpha,
+// beta, flags). The kernel boundary makes the partials visible without any in-kernel fence, sums have a
+// fixed order and results are bitwise reproducible.
 #pragma once
 
 #include "sp_device.h"
@@ -18,7 +19,7 @@
 namespace sp {
 
 // Vector slots of a system.
-enum Slot : int { S_B64 = 0, S_X64, S_T64, S_XLO, S_P, S_R, S_Q, S_T, NSLOT };
+enum Slot : int { S_B64 = 0, S_X64, S_T64, S_XLO, S_P, S_R, S_T, NSLOT };
 
 // Which systems a kernel works on.
 enum Gate : int {
@@ -38,8 +39,8 @@ struct GroupDev {
     Geom g;
     const void* links_lo;
     const void* links64;
-    double* partials;   // [nblk][2 N]
-    unsigned* ticket;
+    double* partials;   // [nblk][2 N] block partials of the last reducing launch
+    double* partials_p; // [nblk][N]   block partials of |p|^2 from the last p update
     int nrhs, sys0, blk0, nblk;
 };
 
@@ -110,49 +111,34 @@ __device__ __forceinline__ Rhs<N> rhs_of(const D& d, const GroupDev& G, int gate
     return h;
 }
 
-// Two-stage reduction of N values per thread over a group's blocks. Returns true in the last block,
-// where thread 0 then holds the group totals in v.
-template <int N>
-__device__ __forceinline__ bool group_reduce(const GroupDev& G, int gblk, double (&v)[N]) {
-    __shared__ int last;
-    block_sum<N>(v);
+// First reduction stage: block totals of NV values per thread, stored by thread 0 as partials[gblk][NV].
+template <int NV>
+__device__ __forceinline__ void block_partials(const GroupDev& G, int gblk, double (&v)[NV]) {
+    block_sum<NV>(v);
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int r = 0; r < N; ++r) G.partials[(size_t)gblk * N + r] = v[r];
-        __threadfence();
-        const unsigned prev = atomicAdd(G.ticket, 1u);
-        last = prev == (unsigned)(G.nblk - 1);
+        for (int k = 0; k < NV; ++k) G.partials[(size_t)gblk * NV + k] = v[k];
     }
-    __syncthreads();
-    if (!last) return false;
-    __threadfence();
-    double s[N];
-#pragma unroll
-    for (int r = 0; r < N; ++r) s[r] = 0.0;
-    for (int b = threadIdx.x; b < G.nblk; b += blockDim.x) {
-#pragma unroll
-        for (int r = 0; r < N; ++r) s[r] += G.partials[(size_t)b * N + r];
-    }
-    block_sum<N>(s);
-    if (threadIdx.x == 0) {
-        *G.ticket = 0u;
-#pragma unroll
-        for (int r = 0; r < N; ++r) v[r] = s[r];
-    }
-    return true;
 }
 
 // ------------------------------------------------------------------------------------------------------
-// Half operator, N right-hand sides sharing each link load.
-//   mode 0: out = D_{p,1-p} in
-//   mode 1: out = m^2 P - D_{p,1-p} in, block partials of Re<P, out> -> alpha = rho / Re<p, A p>
+// Half operator, N right-hand sides sharing each link load. MODE:
+//   DS_PLAIN : out = D_{p,1-p} in
+//   DS_NORM  : t = D_oe p (out), block partials of Re<t, t_stored>; with |p|^2 from the last p update this
+//              gives Re<p, A p> = m^2 |p|^2 + |D_oe p|^2 and alpha, since D_eo = -D_oe^dag for any links
+//   DS_UPDATE: q = m^2 p - D_eo t (not stored); x += alpha p; r -= alpha q; block partials of |r|^2
 // ------------------------------------------------------------------------------------------------------
-template <int LP, int RECON, int VP, int N, class D>
-__global__ __launch_bounds__(256) void k_dslash(D d, int p, int in_slot, int out_slot, int mode, int gate,
-                                                int use64, int remap) {
+enum DsMode : int { DS_PLAIN = 0, DS_NORM = 1, DS_UPDATE = 2 };
+
+template <int LP, int RECON, int VP, int N, class D, int MODE>
+__global__ __launch_bounds__(256) void k_dslash(D d, int p, int in_slot, int out_slot, int gate, int use64,
+                                                int remap) {
     using R = typename Real<VP>::T;
     using LF = LinkFmt<LP, RECON>;
     using VF = VecFmt<VP>;
+    constexpr int XP = VP == F64 ? F64 : F32;  // x: FP64 in place for plain FP64 CG, else the FP32 x_lo
+    using RX = typename Real<XP>::T;
+    using XF = VecFmt<XP>;
     const int lblk = logical_block(remap);
     const int gi = find_group(d, lblk);
     const GroupDev& G = grp_of(d, gi);
@@ -162,12 +148,8 @@ __global__ __launch_bounds__(256) void k_dslash(D d, int p, int in_slot, int out
     const Geom g = G.g;
     const void* links = use64 ? G.links64 : G.links_lo;
     const void* in[N];
-    void* out[N];
 #pragma unroll
-    for (int r = 0; r < N; ++r) {
-        in[r] = h.act[r] ? sys_of(d, G.sys0 + r).v[in_slot] : nullptr;
-        out[r] = h.act[r] ? sys_of(d, G.sys0 + r).v[out_slot] : nullptr;
-    }
+    for (int r = 0; r < N; ++r) in[r] = h.act[r] ? sys_of(d, G.sys0 + r).v[in_slot] : nullptr;
     const int cb = gblk * blockDim.x + threadIdx.x;
     double dots[N];
 #pragma unroll
@@ -205,34 +187,47 @@ __global__ __launch_bounds__(256) void k_dslash(D d, int p, int in_slot, int out
                 acc[r].c[i].re *= R(0.5);
                 acc[r].c[i].im *= R(0.5);
             }
-            if (mode == 0) {
-                VF::store(out[r], g.Vh, cb, acc[r]);
-            } else {
-                const Vec3<R> pc = VF::load(sys_of(d, G.sys0 + r).v[S_P], g.Vh, cb);
-                const R m2 = (R)h.st[r]->m2;
-                Vec3<R> q;
+            const SysDev& S = sys_of(d, G.sys0 + r);
+            if constexpr (MODE == DS_PLAIN) {
+                VF::store(S.v[out_slot], g.Vh, cb, acc[r]);
+            } else if constexpr (MODE == DS_NORM) {
+                const Vec3<R> ts = VF::store_rt(S.v[out_slot], g.Vh, cb, acc[r]);
                 double dd = 0.0;
 #pragma unroll
-                for (int i = 0; i < 3; ++i) {
-                    q.c[i].re = m2 * pc.c[i].re - acc[r].c[i].re;
-                    q.c[i].im = m2 * pc.c[i].im - acc[r].c[i].im;
-                    dd += (double)(pc.c[i].re * q.c[i].re + pc.c[i].im * q.c[i].im);
-                }
+                for (int i = 0; i < 3; ++i)
+                    dd += (double)acc[r].c[i].re * (double)ts.c[i].re + (double)acc[r].c[i].im * (double)ts.c[i].im;
                 dots[r] = dd;
-                VF::store(out[r], g.Vh, cb, q);
+            } else {
+                const Vec3<R> pc = VF::load(S.v[S_P], g.Vh, cb);
+                Vec3<R> rv = VF::load(S.v[S_R], g.Vh, cb);
+                Vec3<RX> xv = XF::load(S.v[XP == F64 ? S_X64 : S_XLO], g.Vh, cb);
+                const R m2 = (R)h.st[r]->m2;
+                const R a = (R)h.st[r]->alpha;
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    const R qre = m2 * pc.c[i].re - acc[r].c[i].re;
+                    const R qim = m2 * pc.c[i].im - acc[r].c[i].im;
+                    xv.c[i].re += (RX)a * (RX)pc.c[i].re;
+                    xv.c[i].im += (RX)a * (RX)pc.c[i].im;
+                    rv.c[i].re -= a * qre;
+                    rv.c[i].im -= a * qim;
+                }
+                XF::store(S.v[XP == F64 ? S_X64 : S_XLO], g.Vh, cb, xv);
+                const Vec3<R> rs = VF::store_rt(S.v[S_R], g.Vh, cb, rv);
+                double dd = 0.0;
+#pragma unroll
+                for (int i = 0; i < 3; ++i)
+                    dd += (double)rs.c[i].re * (double)rs.c[i].re + (double)rs.c[i].im * (double)rs.c[i].im;
+                dots[r] = dd;
             }
         }
     }
-    if (mode == 1 && group_reduce<N>(G, gblk, dots) && threadIdx.x == 0) {
-#pragma unroll
-        for (int r = 0; r < N; ++r)
-            if (h.act[r]) fin_alpha(h.st[r], dots[r]);
-    }
+    if constexpr (MODE != DS_PLAIN) block_partials<N>(G, gblk, dots);
 }
 
 // ------------------------------------------------------------------------------------------------------
 // FP64 true residual on even sites: r = b - m^2 x + D_eo t64, t64 = D_oe x (previous launch).
-// Writes R (inner precision OP) and, when init, P = R; reduces |r|^2 and Re<r, p> -> fin_resid.
+// Writes R (inner precision OP); block partials of |r|^2 and Re<r, p> (p unused when init).
 // ------------------------------------------------------------------------------------------------------
 template <int OP, int N, class D>
 __global__ __launch_bounds__(256) void k_resid(D d, int init, int remap) {
@@ -300,68 +295,13 @@ __global__ __launch_bounds__(256) void k_resid(D d, int init, int remap) {
             dots[2 * r] = dd;
             dots[2 * r + 1] = rp;
             VO::store(S.v[S_R], g.Vh, cb, ro);
-            if (init) VO::store(S.v[S_P], g.Vh, cb, ro);
         }
     }
-    if (group_reduce<2 * N>(G, gblk, dots) && threadIdx.x == 0) {
-#pragma unroll
-        for (int r = 0; r < N; ++r)
-            if (h.act[r]) fin_resid(h.st[r], dots[2 * r], dots[2 * r + 1], init);
-    }
+    block_partials<2 * N>(G, gblk, dots);
 }
 
-// ------------------------------------------------------------------------------------------------------
-// x += alpha p; r -= alpha q; |r|^2 -> fin_update (beta, convergence / reliable-update triggers).
-// x is X64 (FP64) for plain FP64 CG and XLO (FP32) for the mixed solver.
-// ------------------------------------------------------------------------------------------------------
-template <int VP, int XP, int N, class D>
-__global__ __launch_bounds__(256) void k_update(D d, int remap) {
-    using R = typename Real<VP>::T;
-    using RX = typename Real<XP>::T;
-    using VF = VecFmt<VP>;
-    using XF = VecFmt<XP>;
-    const int lblk = logical_block(remap);
-    const int gi = find_group(d, lblk);
-    const GroupDev& G = grp_of(d, gi);
-    const int gblk = lblk - G.blk0;
-    const Rhs<N> h = rhs_of<N>(d, G, G_ITER);
-    if (!h.any) return;
-    const int Vh = G.g.Vh;
-    const int xslot = XP == F64 ? S_X64 : S_XLO;
-    const int cb = gblk * blockDim.x + threadIdx.x;
-    double dots[N];
-#pragma unroll
-    for (int r = 0; r < N; ++r) {
-        dots[r] = 0.0;
-        if (!h.act[r] || cb >= Vh) continue;
-        const SysDev& S = sys_of(d, G.sys0 + r);
-        const double a64 = h.st[r]->alpha;
-        const R a = (R)a64;
-        const Vec3<R> pv = VF::load(S.v[S_P], Vh, cb);
-        const Vec3<R> qv = VF::load(S.v[S_Q], Vh, cb);
-        Vec3<R> rv = VF::load(S.v[S_R], Vh, cb);
-        Vec3<RX> xv = XF::load(S.v[xslot], Vh, cb);
-        double dd = 0.0;
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            xv.c[i].re += (RX)a * (RX)pv.c[i].re;
-            xv.c[i].im += (RX)a * (RX)pv.c[i].im;
-            rv.c[i].re -= a * qv.c[i].re;
-            rv.c[i].im -= a * qv.c[i].im;
-            dd += (double)(rv.c[i].re * rv.c[i].re + rv.c[i].im * rv.c[i].im);
-        }
-        dots[r] = dd;
-        XF::store(S.v[xslot], Vh, cb, xv);
-        VF::store(S.v[S_R], Vh, cb, rv);
-    }
-    if (group_reduce<N>(G, gblk, dots) && threadIdx.x == 0) {
-#pragma unroll
-        for (int r = 0; r < N; ++r)
-            if (h.act[r]) fin_update(h.st[r], dots[r]);
-    }
-}
-
-// p = r + beta p inside an iteration (gate G_ITER); p = a r + beta p after a reliable update (G_XPAY).
+// p = r + beta p inside an iteration (gate G_ITER); p = a r + beta p after a reliable update or at the
+// start (G_XPAY). Block partials of |p|^2 (as stored) feed the next alpha.
 template <int VP, int N, class D>
 __global__ __launch_bounds__(256) void k_xpay(D d, int gate, int remap) {
     using R = typename Real<VP>::T;
@@ -374,21 +314,33 @@ __global__ __launch_bounds__(256) void k_xpay(D d, int gate, int remap) {
     if (!h.any) return;
     const int Vh = G.g.Vh;
     const int cb = gblk * blockDim.x + threadIdx.x;
-    if (cb >= Vh) return;
+    double dots[N];
 #pragma unroll
     for (int r = 0; r < N; ++r) {
-        if (!h.act[r]) continue;
+        dots[r] = 0.0;
+        if (!h.act[r] || cb >= Vh) continue;
         const SysDev& S = sys_of(d, G.sys0 + r);
         const R beta = (R)h.st[r]->beta;
         const R a = gate == G_XPAY ? (R)h.st[r]->xpay_a : R(1);
         const Vec3<R> rv = VF::load(S.v[S_R], Vh, cb);
-        Vec3<R> pv = VF::load(S.v[S_P], Vh, cb);
+        // beta = 0 (start of a solve, restart): p is not read, it may hold anything
+        Vec3<R> pv = beta != R(0) ? VF::load(S.v[S_P], Vh, cb) : vzero<R>();
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
             pv.c[i].re = a * rv.c[i].re + beta * pv.c[i].re;
             pv.c[i].im = a * rv.c[i].im + beta * pv.c[i].im;
         }
-        VF::store(S.v[S_P], Vh, cb, pv);
+        const Vec3<R> ps = VF::store_rt(S.v[S_P], Vh, cb, pv);
+        double dd = 0.0;
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+            dd += (double)ps.c[i].re * (double)ps.c[i].re + (double)ps.c[i].im * (double)ps.c[i].im;
+        dots[r] = dd;
+    }
+    block_sum<N>(dots);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int r = 0; r < N; ++r) G.partials_p[(size_t)gblk * N + r] = dots[r];
     }
 }
 
@@ -420,7 +372,7 @@ __global__ __launch_bounds__(256) void k_accum(D d, int remap) {
     }
 }
 
-// |b|^2 -> bnorm2 and the stopping threshold tol^2 |b|^2.
+// Block partials of |b|^2 (-> bnorm2 and the stopping threshold tol^2 |b|^2).
 template <int N, class D>
 __global__ __launch_bounds__(256) void k_norm_b(D d, int remap) {
     const int lblk = logical_block(remap);
@@ -440,13 +392,54 @@ __global__ __launch_bounds__(256) void k_norm_b(D d, int remap) {
 #pragma unroll
         for (int i = 0; i < 3; ++i) dots[r] += b.c[i].re * b.c[i].re + b.c[i].im * b.c[i].im;
     }
-    if (group_reduce<N>(G, gblk, dots) && threadIdx.x == 0) {
+    block_partials<N>(G, gblk, dots);
+}
+
+// ------------------------------------------------------------------------------------------------------
+// Second reduction stage, one block per group: sum the partials of the previous launch in block order and
+// update the state of every system that launch worked on (same gate, and no state changed in between).
+// ------------------------------------------------------------------------------------------------------
+enum FinKind : int {
+    FIN_ALPHA = 0,
+    FIN_UPDATE = 1,      // inside a chunk
+    FIN_RESID = 2,
+    FIN_RESID_INIT = 3,
+    FIN_NORM_B = 4,
+    FIN_UPDATE_END = 5,  // last iteration of a chunk: also the delta and ru_every triggers
+};
+
+// partials of FIN_ALPHA: |D_oe p|^2 (from DS_NORM) and |p|^2 (from k_xpay)
+
+template <int N, class D>
+__global__ __launch_bounds__(1024) void k_finalize(D d, int kind, int gate) {
+    const GroupDev& G = grp_of(d, blockIdx.x);
+    const Rhs<N> h = rhs_of<N>(d, G, gate);
+    if (!h.any) return;
+    const bool two = kind == FIN_RESID || kind == FIN_RESID_INIT;
+    const int nv = two ? 2 * N : N;
+    // s[0..nv) from partials; for FIN_ALPHA s[N..2N) holds the |p|^2 partials
+    double s[2 * N];
 #pragma unroll
-        for (int r = 0; r < N; ++r) {
-            if (!h.act[r]) continue;
-            h.st[r]->bnorm2 = dots[r];
-            h.st[r]->stop2 = h.st[r]->tol2 * dots[r];
+    for (int k = 0; k < 2 * N; ++k) s[k] = 0.0;
+    for (int b = threadIdx.x; b < G.nblk; b += blockDim.x) {
+#pragma unroll
+        for (int k = 0; k < 2 * N; ++k) {
+            if (k < nv) s[k] += G.partials[(size_t)b * nv + k];
+            else if (kind == FIN_ALPHA) s[k] += G.partials_p[(size_t)b * N + (k - N)];
         }
+    }
+    block_sum<2 * N>(s);
+    if (threadIdx.x != 0) return;
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+        if (!h.act[r]) continue;
+        SolverState* st = h.st[r];
+        if (kind == FIN_ALPHA) fin_alpha(st, st->m2 * s[N + r] + s[r]);
+        else if (kind == FIN_UPDATE || kind == FIN_UPDATE_END) fin_update(st, s[r], kind == FIN_UPDATE_END);
+        else if (kind == FIN_NORM_B) {
+            st->bnorm2 = s[r];
+            st->stop2 = st->tol2 * s[r];
+        } else fin_resid(st, s[2 * r], s[2 * r + 1], kind == FIN_RESID_INIT);
     }
 }
 

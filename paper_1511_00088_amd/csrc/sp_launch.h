@@ -17,20 +17,22 @@ static constexpr int NB = 8;
 
 inline int blocks_for(int n, int nt) { return (n + nt - 1) / nt; }
 
-// Half operator (see k_dslash). D = DescSingle (one system) or DescBatch (up to NB per group).
+// Half operator (see k_dslash; mode DS_PLAIN, DS_NORM or DS_UPDATE). D = DescSingle (one system) or
+// DescBatch (up to NB per group).
 template <class D>
 hipError_t launch_dslash(const D& d, int nblocks, LaunchCfg c, int lp, int recon, int vp, int p, int in_slot,
                          int out_slot, int mode, int gate, int use64, hipStream_t s);
 template <class D>
 hipError_t launch_resid(const D& d, int nblocks, LaunchCfg c, int op, int init, hipStream_t s);
 template <class D>
-hipError_t launch_update(const D& d, int nblocks, LaunchCfg c, int vp, hipStream_t s);
-template <class D>
 hipError_t launch_xpay(const D& d, int nblocks, LaunchCfg c, int vp, int gate, hipStream_t s);
 template <class D>
 hipError_t launch_accum(const D& d, int nblocks, LaunchCfg c, hipStream_t s);
 template <class D>
 hipError_t launch_norm_b(const D& d, int nblocks, LaunchCfg c, hipStream_t s);
+// Second reduction stage (k_finalize), one block per group.
+template <class D>
+hipError_t launch_finalize(const D& d, int ngroups, int kind, int gate, hipStream_t s);
 
 hipError_t launch_pack_gauge(const Geom& g, const double* nat, int prec, int recon, void* out, hipStream_t s);
 hipError_t launch_pack_vec(int Vh, const double* nat, int prec, void* out, hipStream_t s);
@@ -40,9 +42,9 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);  // bytes multiple
 // Force: gamma / force in natural layout from packed FP64 x, lambda (even) and y_x, y_l (odd).
 hipError_t launch_force(const Geom& g, const void* links64, const void* x, const void* lam, const void* yx,
                         const void* yl, double* gamma, double* force, hipStream_t s);
-// out = -2 m Re<lam, x> (device scalar); partials[nblk], ticket zeroed.
+// out = -2 m Re<lam, x> (device scalar), two-stage reduction through partials[mass_grad_blocks(g)].
 hipError_t launch_mass_grad(const Geom& g, double mass, const void* x, const void* lam, double* partials,
-                            unsigned* ticket, double* out, hipStream_t s);
+                            double* out, hipStream_t s);
 int mass_grad_blocks(const Geom& g);
 
 }  // namespace sp

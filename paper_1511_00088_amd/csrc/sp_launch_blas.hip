@@ -19,22 +19,6 @@ struct NOf<DescSingle> {
 };
 
 template <class D>
-hipError_t launch_update(const D& d, int nblocks, LaunchCfg c, int vp, hipStream_t s) {
-    constexpr int N = NOf<D>::value;
-#define SP_LAUNCH(VP, XP)                                                                                  \
-    do {                                                                                                   \
-        hipLaunchKernelGGL((k_update<VP, XP, N, D>), dim3(nblocks), dim3(c.nt), 0, s, d, c.remap);          \
-        return hipGetLastError();                                                                          \
-    } while (0)
-    if (vp == F64) SP_LAUNCH(F64, F64);
-    if (vp == F32) SP_LAUNCH(F32, F32);
-    if (vp == F16) SP_LAUNCH(F16, F32);
-    if (vp == BF16) SP_LAUNCH(BF16, F32);
-#undef SP_LAUNCH
-    return hipErrorInvalidValue;
-}
-
-template <class D>
 hipError_t launch_xpay(const D& d, int nblocks, LaunchCfg c, int vp, int gate, hipStream_t s) {
     constexpr int N = NOf<D>::value;
 #define SP_LAUNCH(VP)                                                                                      \
@@ -64,8 +48,15 @@ hipError_t launch_norm_b(const D& d, int nblocks, LaunchCfg c, hipStream_t s) {
     return hipGetLastError();
 }
 
+template <class D>
+hipError_t launch_finalize(const D& d, int ngroups, int kind, int gate, hipStream_t s) {
+    constexpr int N = NOf<D>::value;
+    hipLaunchKernelGGL((k_finalize<N, D>), dim3(ngroups), dim3(1024), 0, s, d, kind, gate);
+    return hipGetLastError();
+}
+
 #define SP_INST(D)                                                                                         \
-    template hipError_t launch_update<D>(const D&, int, LaunchCfg, int, hipStream_t);                      \
+    template hipError_t launch_finalize<D>(const D&, int, int, int, hipStream_t);                          \
     template hipError_t launch_xpay<D>(const D&, int, LaunchCfg, int, int, hipStream_t);                   \
     template hipError_t launch_accum<D>(const D&, int, LaunchCfg, hipStream_t);                            \
     template hipError_t launch_norm_b<D>(const D&, int, LaunchCfg, hipStream_t);

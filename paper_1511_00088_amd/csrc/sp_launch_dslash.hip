@@ -18,8 +18,15 @@ hipError_t launch_dslash(const D& d, int nblocks, LaunchCfg c, int lp, int recon
     constexpr int N = NOf<D>::value;
 #define SP_LAUNCH(LP, RC, VP)                                                                              \
     do {                                                                                                   \
-        hipLaunchKernelGGL((k_dslash<LP, RC, VP, N, D>), dim3(nblocks), dim3(c.nt), 0, s, d, p, in_slot, \
-                           out_slot, mode, gate, use64, c.remap);                                         \
+        if (mode == DS_PLAIN)                                                                              \
+            hipLaunchKernelGGL((k_dslash<LP, RC, VP, N, D, DS_PLAIN>), dim3(nblocks), dim3(c.nt), 0, s, d, p, \
+                               in_slot, out_slot, gate, use64, c.remap);                                  \
+        else if (mode == DS_NORM)                                                                          \
+            hipLaunchKernelGGL((k_dslash<LP, RC, VP, N, D, DS_NORM>), dim3(nblocks), dim3(c.nt), 0, s, d, p, \
+                               in_slot, out_slot, gate, use64, c.remap);                                  \
+        else                                                                                               \
+            hipLaunchKernelGGL((k_dslash<LP, RC, VP, N, D, DS_UPDATE>), dim3(nblocks), dim3(c.nt), 0, s, d, \
+                               p, in_slot, out_slot, gate, use64, c.remap);                               \
         return hipGetLastError();                                                                          \
     } while (0)
     if (lp == F64 && recon == 18 && vp == F64) SP_LAUNCH(F64, 18, F64);

@@ -51,7 +51,7 @@ def test_workspace_query_and_validation():
     s = _lib.sp_system(ctypes.pointer(lat.geom), ctypes.pointer(g), 0.1, 3, 4)
     prm = _lib.sp_cg_params(1e-8, 100, _lib.SP_F32, 0.1, 0, 50, 0, 1)
     n1 = lib.sp_cg_workspace_bytes(1, ctypes.byref(s), ctypes.byref(prm))
-    assert n1 > 2048 * (3 * 48 + 24 + 4 * 24)
+    assert n1 > 2048 * (3 * 48 + 24 + 3 * 24)
     arr = (_lib.sp_system * 3)(s, s, s)
     n3 = lib.sp_cg_workspace_bytes(3, arr, ctypes.byref(prm))
     assert 3 * (n1 - 100000) < n3 < 3 * n1 + 100000
