@@ -36,6 +36,39 @@ def dslash_bytes_per_site(prec, recon):
     return 8 * LINK_BYTES[(prec, recon)] + 2 * VEC_BYTES[prec]
 
 
+KERNEL_SOURCES = ["paper_1511_00088_amd/csrc/sp_device.h", "paper_1511_00088_amd/csrc/sp_kernels.h",
+                  "paper_1511_00088_amd/csrc/sp_launch_dslash.hip", "paper_1511_00088_amd/tune_mi355x.json"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "dslash_f32_r18_20x20x20x64_traffic.md")
+
+
+def kernel_source_digest():
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per half-Dslash launch from the committed counter summary, or None when the kernel sources
+    or the tuning table changed since the counters were taken."""
+    try:
+        vals = {}
+        with open(TRAFFIC_FILE) as f:
+            for line in f:
+                if "=" in line and line.strip().split("=")[0].strip() in ("traffic_bytes_per_launch",
+                                                                          "kernel_source_digest"):
+                    k, v = (x.strip() for x in line.split("=", 1))
+                    vals[k] = v
+        if vals.get("kernel_source_digest") != kernel_source_digest():
+            return None
+        return float(vals["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def cpu_model():
     try:
         with open("/proc/cpuinfo") as f:
@@ -58,6 +91,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparator solves")
     ap.add_argument("--dslash-reps", type=int, default=200)
+    ap.add_argument("--tune-file", default=os.path.join(ROOT, "paper_1511_00088_amd", "tune_mi355x.json"),
+                    help="tuned launch table to load (tunes in-process when the file is missing)")
+    ap.add_argument("--mode", default="bench", choices=["bench", "traffic"],
+                    help="traffic: only a 1 GiB device copy (counter calibration) and the half-Dslash "
+                         "launches, for hardware-counter runs")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the solver has no multi-GPU path",
@@ -83,11 +121,31 @@ def main():
     G = sp.Gauge(lat, links, lo_prec=args.inner, recon=args.recon)
     G64 = sp.Gauge(lat, links, lo_prec="f64")
     del links
-    log("tuning the half-Dslash launch")
-    sp.tune_dslash(G, args.inner)
-    sp.tune_dslash(G64, "f64")
+    if os.path.exists(args.tune_file):
+        log(f"loading tuned launches from {args.tune_file}")
+        sp.tune_load(args.tune_file)
+    else:
+        log("tuning the half-Dslash launch")
+        sp.tune_dslash(G, args.inner)
+        sp.tune_dslash(G64, "f64")
     ws = sp.Workspace()
     stream = torch.cuda.current_stream()
+
+    if args.mode == "traffic":
+        # calibration: a device-to-device copy of known size, then the dominant kernel alone
+        n = 1 << 30
+        src = torch.ones(n, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        inp = sp.pack_vec(lat, b, args.inner)
+        out = torch.empty_like(inp)
+        for _ in range(20):
+            sp.dslash_packed(G, args.inner, inp, 1, out)
+        torch.cuda.synchronize()
+        print(json.dumps({"mode": "traffic", "copy_bytes": n, "dslash_launches": 20,
+                          "dslash_algorithmic_bytes": dslash_bytes_per_site(args.inner, args.recon) * lat.Vh}))
+        return
 
     def solve_mixed():
         return sp.cg_solve(G, mass, b, tol=tol, inner=args.inner, workspace=ws)
@@ -159,6 +217,10 @@ def main():
     log(f"dslash {args.inner} r{args.recon}: {t_d * 1e6:.2f} us, {achieved:.0f} GB/s, {gflops:.0f} GFLOP/s; "
         f"f64: {t_d64 * 1e6:.2f} us")
 
+    traffic = None
+    if args.inner == "f32" and args.recon == 18 and dims == (20, 20, 20, 64):
+        traffic = measured_traffic()
+
     cpu = None
     if not args.no_cpu:
         import oracle
@@ -204,7 +266,7 @@ def main():
                    "bytes_per_site": bps, "hbm_frac": achieved / HBM_PEAK_GBS, "f64_us": t_d64 * 1e6,
                    "f64_gflops": FLOP_PER_SITE * lat.Vh / t_d64 / 1e9},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
         "cpu_baseline": cpu,
     }
     line.update(extra)

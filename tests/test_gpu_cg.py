@@ -104,3 +104,47 @@ def test_zero_source():
     G = gauge(dims, li.haar_links(dims, 209), "f32")
     x, st = sp.cg_solve(G, 0.1, torch.zeros((128, 3), dtype=torch.complex128, device="cuda:0"), tol=1e-8)
     assert st.converged and st.iters == 0 and float(x.abs().max()) == 0.0
+
+
+_CFG1 = {}
+
+
+def _cfg1():
+    if not _CFG1:
+        _CFG1.update(li.cfg1())
+    return _CFG1
+
+
+def _cfg1_golden():
+    import os
+
+    path = os.path.join(os.path.dirname(__file__), "golden", "cfg1_solution_samples.txt")
+    rows = np.loadtxt(path)
+    cbs = rows[:, 0].astype(np.int64)
+    vals = rows[:, 1::2] + 1j * rows[:, 2::2]
+    return cbs, vals
+
+
+@pytest.mark.parametrize("inner,recon", [("f32", 18), ("f64", 18), ("f32", 12), ("f16", 18), ("bf16", 18)])
+def test_cfg1_full_size_vs_oracle_samples(inner, recon):
+    """20^3x64, m = 0.01, to 1e-8 with the tuned launch the benchmark uses: the solution at the sampled sites
+    against the oracle's 1e-12 solution (golden file written by the oracle alone), and the true residual of
+    the whole GPU solution recomputed by the oracle's operator."""
+    import os
+
+    c = _cfg1()
+    dims, U, m, b = c["dims"], c["links"], c["mass"], c["source"]
+    sp.tune_load(os.path.join(os.path.dirname(os.path.dirname(__file__)), "paper_1511_00088_amd",
+                              "tune_mi355x.json"))
+    announce(f"cfg1 full size {inner} r{recon}")
+    G = gauge(dims, U, inner, recon)
+    x, st = sp.cg_solve(G, m, to_dev(b), tol=1e-8, inner=inner)
+    x = to_host(x)
+    cbs, ref = _cfg1_golden()
+    err = np.linalg.norm(x[cbs] - ref) / np.linalg.norm(ref)
+    res = _true_resid(dims, U, m, b, x)
+    announce(f"  iters={st.iters} ru={st.reliable_updates} resid={st.true_rel_resid:.3e} oracle-resid={res:.3e} "
+             f"sampled err={err:.3e}")
+    assert st.converged and st.true_rel_resid <= 1e-8
+    assert res <= 1.01e-8
+    assert err <= 1e-6
