@@ -38,7 +38,8 @@ def dslash_bytes_per_site(prec, recon):
 
 KERNEL_SOURCES = ["paper_1511_00088_amd/csrc/sp_device.h", "paper_1511_00088_amd/csrc/sp_kernels.h",
                   "paper_1511_00088_amd/csrc/sp_launch_dslash.hip", "paper_1511_00088_amd/tune_mi355x.json"]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "dslash_f32_r18_20x20x20x64_traffic.md")
+def traffic_file(prec, recon, dims):
+    return os.path.join(ROOT, "profiles", f"dslash_{prec}_r{recon}_{dims[0]}x{dims[1]}x{dims[2]}x{dims[3]}_traffic.md")
 
 
 def kernel_source_digest():
@@ -51,12 +52,12 @@ def kernel_source_digest():
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per half-Dslash launch from the committed counter summary, or None when the kernel sources
-    or the tuning table changed since the counters were taken."""
+def measured_traffic(prec, recon, dims):
+    """HBM bytes per half-Dslash launch from the committed counter summary, or None when there is none or
+    the kernel sources or the tuning table changed since the counters were taken."""
     try:
         vals = {}
-        with open(TRAFFIC_FILE) as f:
+        with open(traffic_file(prec, recon, dims)) as f:
             for line in f:
                 if "=" in line and line.strip().split("=")[0].strip() in ("traffic_bytes_per_launch",
                                                                           "kernel_source_digest"):
@@ -67,6 +68,60 @@ def measured_traffic():
         return float(vals["traffic_bytes_per_launch"])
     except (OSError, KeyError, ValueError):
         return None
+
+
+def bench_batched(sp, li, torch, dev, log):
+    """The batched workload: 8 right-hand sides on the 20^3x64 field plus 24 systems on 8^4, 12^3x24 and
+    16^3x32 (masses uniform in [0.01, 0.1]), FP32 + FP64 reliable updates, solved together and one by one."""
+    gauges, systems = li.uneven_batch()
+    G = []
+    for dims, U in gauges:
+        G.append(sp.Gauge(sp.Lattice(dims), torch.from_numpy(U).to(dev), lo_prec="f32", recon=18))
+    sysl = [(G[s.gauge_index], s.mass, torch.from_numpy(s.source).to(dev)) for s in systems]
+    ws = sp.Workspace()
+    sp.cg_solve_batched(sysl, tol=1e-8, inner="f32", workspace=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    xs, st = sp.cg_solve_batched(sysl, tol=1e-8, inner="f32", workspace=ws)
+    torch.cuda.synchronize()
+    t_b = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    err = 0.0
+    for (g, m, bb), xb in zip(sysl, xs):
+        x1, _ = sp.cg_solve(g, m, bb, tol=1e-8, inner="f32", workspace=ws)
+        err = max(err, float(torch.linalg.norm(x1 - xb) / torch.linalg.norm(x1)))
+    torch.cuda.synchronize()
+    t_s = time.perf_counter() - t0
+    ok = all(s.converged for s in st)
+    log(f"batched 32 systems: {t_b * 1e3:.1f} ms together, {t_s * 1e3:.1f} ms one by one, all converged={ok}")
+    return {"systems": len(sysl), "s": t_b, "one_by_one_s": t_s, "speedup": t_s / t_b, "all_converged": ok,
+            "max_iters": max(s.iters for s in st), "max_rel_diff_vs_single": err}
+
+
+def bench_gradient(sp, li, torch, dev, log):
+    """16^3x32, m = 0.05: loss Re phi^dag A^-1 phi, forward solve + adjoint solve + force kernels."""
+    c = li.cfg4()
+    lat = sp.Lattice(c["dims"])
+    U = torch.from_numpy(c["links"]).to(dev).requires_grad_(True)
+    phi = torch.from_numpy(c["source"]).to(dev).requires_grad_(True)
+    m = torch.tensor(c["mass"], dtype=torch.float64, device=dev, requires_grad=True)
+
+    def step():
+        x = sp.staggered_solve(U, m, phi, lat, inner="f32", tol=1e-10)
+        loss = torch.vdot(phi.flatten(), x.flatten()).real
+        loss.backward()
+        return loss
+
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        U.grad = None
+        step()
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / 3
+    log(f"gradient 16^3x32: {t * 1e3:.1f} ms forward + backward")
+    return {"dims": list(c["dims"]), "s": t, "note": "forward solve + adjoint solve to 1e-10 + force kernels"}
 
 
 def cpu_model():
@@ -86,11 +141,14 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--inner", default="f32", choices=["f32", "f16", "bf16"])
-    ap.add_argument("--recon", type=int, default=18, choices=[18, 12])
+    ap.add_argument("--recon", type=int, default=12, choices=[18, 12],
+                    help="link storage: 12 = first two rows, third rebuilt as conj(row0 x row1) (exact for SU(3))")
     ap.add_argument("--dims", type=int, nargs=4, default=[20, 20, 20, 64])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparator solves")
     ap.add_argument("--dslash-reps", type=int, default=200)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the 16-bit storage solves, the batched workload and the gradient timing")
     ap.add_argument("--tune-file", default=os.path.join(ROOT, "paper_1511_00088_amd", "tune_mi355x.json"),
                     help="tuned launch table to load (tunes in-process when the file is missing)")
     ap.add_argument("--mode", default="bench", choices=["bench", "traffic"],
@@ -120,7 +178,10 @@ def main():
     b = torch.from_numpy(c["source"]).to(dev)
     G = sp.Gauge(lat, links, lo_prec=args.inner, recon=args.recon)
     G64 = sp.Gauge(lat, links, lo_prec="f64")
-    del links
+    links_cache = [links]
+
+    def G64_links():
+        return links_cache[0]
     if os.path.exists(args.tune_file):
         log(f"loading tuned launches from {args.tune_file}")
         sp.tune_load(args.tune_file)
@@ -217,9 +278,30 @@ def main():
     log(f"dslash {args.inner} r{args.recon}: {t_d * 1e6:.2f} us, {achieved:.0f} GB/s, {gflops:.0f} GFLOP/s; "
         f"f64: {t_d64 * 1e6:.2f} us")
 
-    traffic = None
-    if args.inner == "f32" and args.recon == 18 and dims == (20, 20, 20, 64):
-        traffic = measured_traffic()
+    traffic = measured_traffic(args.inner, args.recon, dims)
+
+    if not args.no_extras and "err_mixed_vs_fp64_1e12" in extra:
+        # 16-bit storage of links and vectors with FP32 arithmetic, same workload
+        low = {}
+        for prec in ("f16", "bf16"):
+            for rc in (18, 12):
+                Gl = sp.Gauge(lat, G64_links(), lo_prec=prec, recon=rc)
+                sp.cg_solve(Gl, mass, b, tol=tol, inner=prec, workspace=ws)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                nrep = 3
+                for _ in range(nrep):
+                    xl, stl = sp.cg_solve(Gl, mass, b, tol=tol, inner=prec, workspace=ws)
+                torch.cuda.synchronize()
+                tl = (time.perf_counter() - t0) / nrep
+                el = float(torch.linalg.norm(xl - xref) / torch.linalg.norm(xref))
+                low[f"{prec}_r{rc}"] = {"s": tl, "iters": stl.iters, "reliable_updates": stl.reliable_updates,
+                                        "true_rel_resid": stl.true_rel_resid, "err_vs_fp64_1e12": el}
+                log(f"{prec} r{rc}: {tl * 1e3:.2f} ms/solve iters={stl.iters} err={el:.2e}")
+                del Gl
+        extra["storage_16bit"] = low
+        extra["batched"] = bench_batched(sp, li, torch, dev, log)
+        extra["gradient"] = bench_gradient(sp, li, torch, dev, log)
 
     cpu = None
     if not args.no_cpu:

@@ -9,7 +9,7 @@
 //
 // Global dot products use a two-stage reduction: each block reduces its sites in FP64 (wave64 shuffles,
 // then LDS across waves) and stores one partial per system; the next launch, k_finalize (one block per
-// group), sums the partials in block order and updates each system's device-resident state (alpha,
+// group), sums the partials in a fixed order and updates each system's device-resident state (alpha,
 // beta, flags). The kernel boundary makes the partials visible without any in-kernel fence, sums have a
 // fixed order and results are bitwise reproducible.
 #pragma once
@@ -409,7 +409,10 @@ enum FinKind : int {
 };
 
 // partials of FIN_ALPHA: |D_oe p|^2 (from DS_NORM) and |p|^2 (from k_xpay)
-
+//
+// The launch is latency bound: 1024 threads put every partial load in flight at once (a few per thread),
+// and for a single system the state is read into registers while they are in flight and written back
+// once.
 template <int N, class D>
 __global__ __launch_bounds__(1024) void k_finalize(D d, int kind, int gate) {
     const GroupDev& G = grp_of(d, blockIdx.x);
@@ -417,6 +420,8 @@ __global__ __launch_bounds__(1024) void k_finalize(D d, int kind, int gate) {
     if (!h.any) return;
     const bool two = kind == FIN_RESID || kind == FIN_RESID_INIT;
     const int nv = two ? 2 * N : N;
+    SolverState loc;
+    if constexpr (N == 1) loc = *h.st[0];
     // s[0..nv) from partials; for FIN_ALPHA s[N..2N) holds the |p|^2 partials
     double s[2 * N];
 #pragma unroll
@@ -433,7 +438,7 @@ __global__ __launch_bounds__(1024) void k_finalize(D d, int kind, int gate) {
 #pragma unroll
     for (int r = 0; r < N; ++r) {
         if (!h.act[r]) continue;
-        SolverState* st = h.st[r];
+        SolverState* st = N == 1 ? &loc : h.st[r];
         if (kind == FIN_ALPHA) fin_alpha(st, st->m2 * s[N + r] + s[r]);
         else if (kind == FIN_UPDATE || kind == FIN_UPDATE_END) fin_update(st, s[r], kind == FIN_UPDATE_END);
         else if (kind == FIN_NORM_B) {
@@ -441,6 +446,7 @@ __global__ __launch_bounds__(1024) void k_finalize(D d, int kind, int gate) {
             st->stop2 = st->tol2 * s[r];
         } else fin_resid(st, s[2 * r], s[2 * r + 1], kind == FIN_RESID_INIT);
     }
+    if constexpr (N == 1) *h.st[0] = loc;
 }
 
 // ------------------------------------------------------------------------------------------------------
