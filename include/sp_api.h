@@ -160,7 +160,7 @@ int sp_cg_solve(const sp_geom* g, const sp_gauge* U, double mass, const double* 
                 const sp_cg_params* params, sp_cg_stats* stats, void* ws, size_t ws_bytes, void* stream);
 
 /* Solve nsys independent systems together: systems sharing a gauge field and geometry form groups of up
- * to 8 right-hand sides; all groups advance in one launch per kernel, captured in a hipGraph per chunk
+ * to 4 right-hand sides; all groups advance in one launch per kernel, captured in a hipGraph per chunk
  * of iterations; converged systems stop updating while the others continue. stats: host array of nsys
  * (nullable). Returns SP_OK if every system converged, SP_NOT_CONVERGED if any did not, or an error.
  * Synchronous with respect to stream. */
@@ -184,6 +184,16 @@ size_t sp_force_workspace_bytes(const sp_geom* g);
 int sp_cg_force(const sp_geom* g, const sp_gauge* U, double mass, const double* x_e,
                 const double* lambda_e, double* gamma, double* force, double* grad_mass, void* ws,
                 size_t ws_bytes, void* stream);
+
+/* Workspace bytes for sp_full_solve. */
+size_t sp_full_workspace_bytes(const sp_geom* g, const sp_gauge* U, const sp_cg_params* params);
+
+/* Full-lattice solve (m + D) psi = src, the system the even-odd solve is carved from: with M split by
+ * parity, b_e = m src_e - D_eo src_o, (m^2 - D_eo D_oe) psi_e = b_e (solved as sp_cg_solve with params),
+ * psi_o = (src_o - D_oe psi_e) / m. src, psi: device natural [V][3] complex128 (lex order). mass must
+ * be non-zero. Returns the even solve's status. Synchronous with respect to stream. */
+int sp_full_solve(const sp_geom* g, const sp_gauge* U, double mass, const double* src, double* psi,
+                  const sp_cg_params* params, sp_cg_stats* stats, void* ws, size_t ws_bytes, void* stream);
 
 /* Autotune the half-operator launch (block size, XCD-aware block order) for (g, prec, U->recon) by
  * timing it with HIP events on stream; in and out are scratch packed vectors of that precision. The

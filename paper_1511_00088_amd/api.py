@@ -205,6 +205,30 @@ def cg_solve_batched(systems, tol: float = 1e-8, inner="f32", max_iter: int = 10
     return xs, [_stats(s) for s in st]
 
 
+def full_solve(gauge: Gauge, mass: float, src: torch.Tensor, tol: float = 1e-8, inner="f32",
+               max_iter: int = 100000, delta: float = 0.1, ru_every: int = 0, poll_chunk: int = 0,
+               use_graph: bool = True):
+    """Solve (m + D) psi = src on the whole lattice (src, psi: complex128 [V][3] in lex order) through the
+    even-odd system. Returns (psi, SolveStats of the even solve)."""
+    lat = gauge.lat
+    _check_c128(src, (lat.V, 3), "src")
+    inner_p = _prec(inner)
+    if inner_p != L.SP_F64 and inner_p != gauge.lo_prec:
+        raise ValueError("the gauge field's low-precision packing must match the inner precision")
+    prm = _params(tol, max_iter, inner_p, delta, ru_every, poll_chunk, 0, use_graph)
+    lib = L.load()
+    nbytes = lib.sp_full_workspace_bytes(ctypes.byref(lat.geom), ctypes.byref(gauge.struct), ctypes.byref(prm))
+    if nbytes == 0:
+        raise L.StagError(L.SP_ERR_INVALID_ARG, "sp_full_workspace_bytes")
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=src.device)
+    psi = torch.empty_like(src)
+    st = L.sp_cg_stats()
+    rc = lib.sp_full_solve(ctypes.byref(lat.geom), ctypes.byref(gauge.struct), float(mass), _ptr(src), _ptr(psi),
+                           ctypes.byref(prm), ctypes.byref(st), _ptr(ws), ctypes.c_size_t(nbytes), _stream())
+    L.check(rc, "sp_full_solve", allow_not_converged=True)
+    return psi, _stats(st)
+
+
 def cg_force(gauge: Gauge, mass: float, x: torch.Tensor, lam: torch.Tensor, want_force: bool = True):
     """Link gradient gamma = dl/dU, su(3) force TA(U gamma^dag) and dl/dm = -2 m Re<lam, x>."""
     lat = gauge.lat

@@ -899,3 +899,60 @@ int sp_cg_force(const sp_geom* g, const sp_gauge* U, double mass, const double* 
 }
 
 }  // extern "C"
+
+extern "C" {
+
+size_t sp_full_workspace_bytes(const sp_geom* g, const sp_gauge* U, const sp_cg_params* params) {
+    Geom G;
+    if (check_geom(g, &G) || !U || !params) return 0;
+    sp_system s;
+    s.g = g;
+    s.U = U;
+    s.mass = 1.0;
+    s.b_e = nullptr;
+    s.x_e = nullptr;
+    const size_t cg = sp_cg_workspace_bytes(1, &s, params);
+    if (cg == 0) return 0;
+    return 6 * align256((size_t)G.Vh * 48) + cg;
+}
+
+int sp_full_solve(const sp_geom* g, const sp_gauge* U, double mass, const double* src, double* psi,
+                  const sp_cg_params* params, sp_cg_stats* stats, void* ws, size_t ws_bytes, void* stream) {
+    Geom G;
+    int rc = check_geom(g, &G);
+    if (rc) return rc;
+    if (!U || !U->f64 || !src || !psi || !params) return fail(SP_ERR_INVALID_ARG, "null pointer");
+    if (!std::isfinite(mass) || mass == 0.0) return fail(SP_ERR_INVALID_ARG, "mass must be finite and non-zero");
+    const size_t need = sp_full_workspace_bytes(g, U, params);
+    if (need == 0) return fail(SP_ERR_INVALID_ARG, "bad parameters");
+    if (!ws || ws_bytes < need) return fail(SP_ERR_WORKSPACE, "workspace %zu bytes < required %zu", ws_bytes, need);
+    if (((uintptr_t)ws) & 255) return fail(SP_ERR_INVALID_ARG, "workspace not 256-byte aligned");
+    hipStream_t s = (hipStream_t)stream;
+    const size_t v = align256((size_t)G.Vh * 48);
+    char* base = (char*)ws;
+    void* se = base;
+    void* so = base + v;
+    void* t = base + 2 * v;
+    void* pe = base + 3 * v;
+    double* be = (double*)(base + 4 * v);
+    double* xe = (double*)(base + 5 * v);
+    void* wcg = base + 6 * v;
+    sp_gauge U64 = *U;
+    U64.lo = U->f64;
+    U64.lo_prec = SP_F64;
+    U64.recon = 18;
+    HIP_TRY(launch_full_split(G, src, se, so, s));
+    if ((rc = sp_dslash(g, &U64, SP_F64, so, t, 0, stream))) return rc;  // t = D_eo src_o
+    HIP_TRY(launch_full_source(G, mass, se, t, be, s));
+    sp_cg_params prm = *params;
+    prm.use_x0 = 0;  // psi_e starts from zero (the buffer is workspace, not a guess)
+    const int st = sp_cg_solve(g, U, mass, be, xe, &prm, stats, wcg, ws_bytes - 6 * v, stream);
+    if (st < 0) return st;
+    HIP_TRY(launch_pack_vec(G.Vh, xe, SP_F64, pe, s));
+    if ((rc = sp_dslash(g, &U64, SP_F64, pe, t, 1, stream))) return rc;  // t = D_oe psi_e
+    HIP_TRY(launch_full_merge(G, mass, xe, so, t, psi, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return st;
+}
+
+}  // extern "C"

@@ -130,6 +130,10 @@ __device__ __forceinline__ void block_partials(const GroupDev& G, int gblk, doub
 // ------------------------------------------------------------------------------------------------------
 enum DsMode : int { DS_PLAIN = 0, DS_NORM = 1, DS_UPDATE = 2 };
 
+// Multi-system launches keep every load unconditional so that the compiler can keep all of them in flight:
+// right-hand sides beyond the group's count read the last system's vectors and store nothing, and systems
+// that are stopped or paused are computed with zero coefficients (x += 0 p, r -= 0 q, p = 0 r + 1 p leave
+// their stored values unchanged). Only temporaries (t) are overwritten for them.
 template <int LP, int RECON, int VP, int N, class D, int MODE>
 __global__ __launch_bounds__(256) void k_dslash(D d, int p, int in_slot, int out_slot, int gate, int use64,
                                                 int remap) {
@@ -146,10 +150,11 @@ __global__ __launch_bounds__(256) void k_dslash(D d, int p, int in_slot, int out
     const Rhs<N> h = rhs_of<N>(d, G, gate);
     if (!h.any) return;
     const Geom g = G.g;
+    const int nr = G.nrhs;
     const void* links = use64 ? G.links64 : G.links_lo;
     const void* in[N];
 #pragma unroll
-    for (int r = 0; r < N; ++r) in[r] = h.act[r] ? sys_of(d, G.sys0 + r).v[in_slot] : nullptr;
+    for (int r = 0; r < N; ++r) in[r] = sys_of(d, G.sys0 + (r < nr ? r : nr - 1)).v[in_slot];
     const int cb = gblk * blockDim.x + threadIdx.x;
     double dots[N];
 #pragma unroll
@@ -160,7 +165,8 @@ __global__ __launch_bounds__(256) void k_dslash(D d, int p, int in_slot, int out
         Vec3<R> acc[N];
 #pragma unroll
         for (int r = 0; r < N; ++r) acc[r] = vzero<R>();
-#pragma unroll
+// one direction at a time for several systems (their gathers would not fit in registers otherwise)
+#pragma unroll(N == 1 ? 4 : 1)
         for (int mu = 0; mu < 4; ++mu) {
             R e = (R)eta_sign(s, mu);
             R sf = e, sb = -e;
@@ -171,54 +177,82 @@ __global__ __launch_bounds__(256) void k_dslash(D d, int p, int in_slot, int out
             const int nf = nbr(g, s, mu, +1);
             const int nb = nbr(g, s, mu, -1);
             const Su3<R> Uf = LF::load(link_block<LF>(links, g.Vh, p, mu), g.Vh, cb);
+            Vec3<R> v[N];
 #pragma unroll
-            for (int r = 0; r < N; ++r)
-                if (h.act[r]) mv_acc(acc[r], Uf, VF::load(in[r], g.Vh, nf), sf);
+            for (int r = 0; r < N; ++r) v[r] = VF::load(in[r], g.Vh, nf);
+#pragma unroll
+            for (int r = 0; r < N; ++r) mv_acc(acc[r], Uf, v[r], sf);
             const Su3<R> Ub = LF::load(link_block<LF>(links, g.Vh, 1 - p, mu), g.Vh, nb);
 #pragma unroll
-            for (int r = 0; r < N; ++r)
-                if (h.act[r]) mdv_acc(acc[r], Ub, VF::load(in[r], g.Vh, nb), sb);
+            for (int r = 0; r < N; ++r) v[r] = VF::load(in[r], g.Vh, nb);
+#pragma unroll
+            for (int r = 0; r < N; ++r) mdv_acc(acc[r], Ub, v[r], sb);
         }
 #pragma unroll
-        for (int r = 0; r < N; ++r) {
-            if (!h.act[r]) continue;
+        for (int r = 0; r < N; ++r)
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
                 acc[r].c[i].re *= R(0.5);
                 acc[r].c[i].im *= R(0.5);
             }
-            const SysDev& S = sys_of(d, G.sys0 + r);
-            if constexpr (MODE == DS_PLAIN) {
-                VF::store(S.v[out_slot], g.Vh, cb, acc[r]);
-            } else if constexpr (MODE == DS_NORM) {
-                const Vec3<R> ts = VF::store_rt(S.v[out_slot], g.Vh, cb, acc[r]);
+        if constexpr (MODE == DS_PLAIN) {
+#pragma unroll
+            for (int r = 0; r < N; ++r)
+                if (r < nr) VF::store(sys_of(d, G.sys0 + r).v[out_slot], g.Vh, cb, acc[r]);
+        } else if constexpr (MODE == DS_NORM) {
+#pragma unroll
+            for (int r = 0; r < N; ++r) {
+                if (r >= nr) continue;
+                const Vec3<R> ts = VF::store_rt(sys_of(d, G.sys0 + r).v[out_slot], g.Vh, cb, acc[r]);
                 double dd = 0.0;
 #pragma unroll
                 for (int i = 0; i < 3; ++i)
                     dd += (double)acc[r].c[i].re * (double)ts.c[i].re + (double)acc[r].c[i].im * (double)ts.c[i].im;
                 dots[r] = dd;
-            } else {
-                const Vec3<R> pc = VF::load(S.v[S_P], g.Vh, cb);
-                Vec3<R> rv = VF::load(S.v[S_R], g.Vh, cb);
-                Vec3<RX> xv = XF::load(S.v[XP == F64 ? S_X64 : S_XLO], g.Vh, cb);
-                const R m2 = (R)h.st[r]->m2;
-                const R a = (R)h.st[r]->alpha;
+            }
+        } else {
+            // per group of up to four systems: loads first, then arithmetic, then stores
+            constexpr int NG = N < 4 ? N : 4;
 #pragma unroll
-                for (int i = 0; i < 3; ++i) {
-                    const R qre = m2 * pc.c[i].re - acc[r].c[i].re;
-                    const R qim = m2 * pc.c[i].im - acc[r].c[i].im;
-                    xv.c[i].re += (RX)a * (RX)pc.c[i].re;
-                    xv.c[i].im += (RX)a * (RX)pc.c[i].im;
-                    rv.c[i].re -= a * qre;
-                    rv.c[i].im -= a * qim;
+            for (int r0 = 0; r0 < N; r0 += NG) {
+                Vec3<R> pc[NG], rv[NG];
+                Vec3<RX> xv[NG];
+#pragma unroll
+                for (int j = 0; j < NG; ++j) {
+                    const int r = r0 + j;
+                    const SysDev& S = sys_of(d, G.sys0 + (r < nr ? r : nr - 1));
+                    pc[j] = VF::load(S.v[S_P], g.Vh, cb);
+                    rv[j] = VF::load(S.v[S_R], g.Vh, cb);
+                    xv[j] = XF::load(S.v[XP == F64 ? S_X64 : S_XLO], g.Vh, cb);
                 }
-                XF::store(S.v[XP == F64 ? S_X64 : S_XLO], g.Vh, cb, xv);
-                const Vec3<R> rs = VF::store_rt(S.v[S_R], g.Vh, cb, rv);
-                double dd = 0.0;
 #pragma unroll
-                for (int i = 0; i < 3; ++i)
-                    dd += (double)rs.c[i].re * (double)rs.c[i].re + (double)rs.c[i].im * (double)rs.c[i].im;
-                dots[r] = dd;
+                for (int j = 0; j < NG; ++j) {
+                    const int r = r0 + j;
+                    const R m2 = h.act[r] ? (R)h.st[r]->m2 : R(0);
+                    const R a = h.act[r] ? (R)h.st[r]->alpha : R(0);
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) {
+                        const R qre = m2 * pc[j].c[i].re - acc[r].c[i].re;
+                        const R qim = m2 * pc[j].c[i].im - acc[r].c[i].im;
+                        xv[j].c[i].re += (RX)a * (RX)pc[j].c[i].re;
+                        xv[j].c[i].im += (RX)a * (RX)pc[j].c[i].im;
+                        rv[j].c[i].re -= a * qre;
+                        rv[j].c[i].im -= a * qim;
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < NG; ++j) {
+                    const int r = r0 + j;
+                    if (r >= nr) continue;
+                    const SysDev& S = sys_of(d, G.sys0 + r);
+                    XF::store(S.v[XP == F64 ? S_X64 : S_XLO], g.Vh, cb, xv[j]);
+                    const Vec3<R> rs = VF::store_rt(S.v[S_R], g.Vh, cb, rv[j]);
+                    double dd = 0.0;
+#pragma unroll
+                    for (int i = 0; i < 3; ++i)
+                        dd += (double)rs.c[i].re * (double)rs.c[i].re + (double)rs.c[i].im * (double)rs.c[i].im;
+                    dots[r] = dd;
+                }
             }
         }
     }
@@ -313,29 +347,42 @@ __global__ __launch_bounds__(256) void k_xpay(D d, int gate, int remap) {
     const Rhs<N> h = rhs_of<N>(d, G, gate);
     if (!h.any) return;
     const int Vh = G.g.Vh;
+    const int nr = G.nrhs;
     const int cb = gblk * blockDim.x + threadIdx.x;
     double dots[N];
 #pragma unroll
-    for (int r = 0; r < N; ++r) {
-        dots[r] = 0.0;
-        if (!h.act[r] || cb >= Vh) continue;
-        const SysDev& S = sys_of(d, G.sys0 + r);
-        const R beta = (R)h.st[r]->beta;
-        const R a = gate == G_XPAY ? (R)h.st[r]->xpay_a : R(1);
-        const Vec3<R> rv = VF::load(S.v[S_R], Vh, cb);
-        // beta = 0 (start of a solve, restart): p is not read, it may hold anything
-        Vec3<R> pv = beta != R(0) ? VF::load(S.v[S_P], Vh, cb) : vzero<R>();
+    for (int r = 0; r < N; ++r) dots[r] = 0.0;
+    if (cb < Vh) {
+        // every load first (systems that do not update take p = 0 r + 1 p), then arithmetic, then stores
+        Vec3<R> rv[N], pv[N];
+        R a[N], beta[N];
 #pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            pv.c[i].re = a * rv.c[i].re + beta * pv.c[i].re;
-            pv.c[i].im = a * rv.c[i].im + beta * pv.c[i].im;
+        for (int r = 0; r < N; ++r) {
+            const SysDev& S = sys_of(d, G.sys0 + (r < nr ? r : nr - 1));
+            beta[r] = h.act[r] ? (R)h.st[r]->beta : R(1);
+            a[r] = h.act[r] ? (gate == G_XPAY ? (R)h.st[r]->xpay_a : R(1)) : R(0);
+            rv[r] = VF::load(S.v[S_R], Vh, cb);
+            // beta = 0 (start of a solve, restart): p is not read, it may hold anything
+            pv[r] = beta[r] != R(0) ? VF::load(S.v[S_P], Vh, cb) : vzero<R>();
         }
-        const Vec3<R> ps = VF::store_rt(S.v[S_P], Vh, cb, pv);
-        double dd = 0.0;
 #pragma unroll
-        for (int i = 0; i < 3; ++i)
-            dd += (double)ps.c[i].re * (double)ps.c[i].re + (double)ps.c[i].im * (double)ps.c[i].im;
-        dots[r] = dd;
+        for (int r = 0; r < N; ++r) {
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                pv[r].c[i].re = a[r] * rv[r].c[i].re + beta[r] * pv[r].c[i].re;
+                pv[r].c[i].im = a[r] * rv[r].c[i].im + beta[r] * pv[r].c[i].im;
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < N; ++r) {
+            if (r >= nr) continue;
+            const Vec3<R> ps = VF::store_rt(sys_of(d, G.sys0 + r).v[S_P], Vh, cb, pv[r]);
+            double dd = 0.0;
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+                dd += (double)ps.c[i].re * (double)ps.c[i].re + (double)ps.c[i].im * (double)ps.c[i].im;
+            dots[r] = dd;
+        }
     }
     block_sum<N>(dots);
     if (threadIdx.x == 0) {
@@ -410,9 +457,8 @@ enum FinKind : int {
 
 // partials of FIN_ALPHA: |D_oe p|^2 (from DS_NORM) and |p|^2 (from k_xpay)
 //
-// The launch is latency bound: 1024 threads put every partial load in flight at once (a few per thread),
-// and for a single system the state is read into registers while they are in flight and written back
-// once.
+// The launch is latency bound: 1024 threads put every partial load in flight at once (a few per thread);
+// then thread r updates the state of system r.
 template <int N, class D>
 __global__ __launch_bounds__(1024) void k_finalize(D d, int kind, int gate) {
     const GroupDev& G = grp_of(d, blockIdx.x);
@@ -420,8 +466,6 @@ __global__ __launch_bounds__(1024) void k_finalize(D d, int kind, int gate) {
     if (!h.any) return;
     const bool two = kind == FIN_RESID || kind == FIN_RESID_INIT;
     const int nv = two ? 2 * N : N;
-    SolverState loc;
-    if constexpr (N == 1) loc = *h.st[0];
     // s[0..nv) from partials; for FIN_ALPHA s[N..2N) holds the |p|^2 partials
     double s[2 * N];
 #pragma unroll
@@ -434,19 +478,30 @@ __global__ __launch_bounds__(1024) void k_finalize(D d, int kind, int gate) {
         }
     }
     block_sum<2 * N>(s);
-    if (threadIdx.x != 0) return;
+    // thread r updates system r (the states are independent, their loads overlap)
+    __shared__ double tot[2 * N];
+    if (threadIdx.x == 0) {
 #pragma unroll
-    for (int r = 0; r < N; ++r) {
-        if (!h.act[r]) continue;
-        SolverState* st = N == 1 ? &loc : h.st[r];
-        if (kind == FIN_ALPHA) fin_alpha(st, st->m2 * s[N + r] + s[r]);
-        else if (kind == FIN_UPDATE || kind == FIN_UPDATE_END) fin_update(st, s[r], kind == FIN_UPDATE_END);
-        else if (kind == FIN_NORM_B) {
-            st->bnorm2 = s[r];
-            st->stop2 = st->tol2 * s[r];
-        } else fin_resid(st, s[2 * r], s[2 * r + 1], kind == FIN_RESID_INIT);
+        for (int k = 0; k < 2 * N; ++k) tot[k] = s[k];
     }
-    if constexpr (N == 1) *h.st[0] = loc;
+    __syncthreads();
+    const int r = threadIdx.x;
+    if (r >= N || r >= G.nrhs) return;
+    bool act = false;
+    SolverState* st = nullptr;
+#pragma unroll
+    for (int q = 0; q < N; ++q)
+        if (q == r) {
+            act = h.act[q];
+            st = h.st[q];
+        }
+    if (!act) return;
+    if (kind == FIN_ALPHA) fin_alpha(st, st->m2 * tot[N + r] + tot[r]);
+    else if (kind == FIN_UPDATE || kind == FIN_UPDATE_END) fin_update(st, tot[r], kind == FIN_UPDATE_END);
+    else if (kind == FIN_NORM_B) {
+        st->bnorm2 = tot[r];
+        st->stop2 = st->tol2 * tot[r];
+    } else fin_resid(st, tot[2 * r], tot[2 * r + 1], kind == FIN_RESID_INIT);
 }
 
 // ------------------------------------------------------------------------------------------------------

@@ -13,7 +13,7 @@ struct LaunchCfg {
 };
 
 // Maximum systems per group in batched launches.
-static constexpr int NB = 8;
+static constexpr int NB = 4;
 
 inline int blocks_for(int n, int nt) { return (n + nt - 1) / nt; }
 
@@ -46,5 +46,12 @@ hipError_t launch_force(const Geom& g, const void* links64, const void* x, const
 hipError_t launch_mass_grad(const Geom& g, double mass, const void* x, const void* lam, double* partials,
                             double* out, hipStream_t s);
 int mass_grad_blocks(const Geom& g);
+
+// Full-lattice solve helpers (sp_full.hip): split a natural full vector into packed FP64 halves, form
+// b_e = m src_e - t_e in the natural half layout, merge psi_e with psi_o = (src_o - t_o) / m.
+hipError_t launch_full_split(const Geom& g, const double* src, void* se, void* so, hipStream_t s);
+hipError_t launch_full_source(const Geom& g, double m, const void* se, const void* te, double* be, hipStream_t s);
+hipError_t launch_full_merge(const Geom& g, double m, const double* psie, const void* so, const void* to,
+                             double* psi, hipStream_t s);
 
 }  // namespace sp

@@ -148,3 +148,33 @@ def test_cfg1_full_size_vs_oracle_samples(inner, recon):
     assert st.converged and st.true_rel_resid <= 1e-8
     assert res <= 1.01e-8
     assert err <= 1e-6
+
+
+@pytest.mark.parametrize("dims,bc_t,inner,links", [((4, 4, 4, 4), 0, "f64", "haar"), ((8, 6, 4, 10), 1, "f32", "near"),
+                                                   ((8, 8, 8, 8), 0, "f16", "near"), ((6, 4, 4, 8), 0, "bf16", "haar")])
+def test_full_system_solve(dims, bc_t, inner, links):
+    """(m + D) psi = src on the whole lattice: source preparation, even solve and odd reconstruction on the
+    GPU against the oracle's full solve (pinned by dense solves), plus the full residual via the oracle's D."""
+    announce(f"full solve dims={dims} bc_t={bc_t} {inner}")
+    V = li.volume(dims)
+    U = li.haar_links(dims, 501) if links == "haar" else li.near_identity_links(dims, 0.3, 501)
+    src = li.gaussian_vector(V, 502)
+    m = 0.1
+    G = gauge(dims, U, inner, 18, bc_t)
+    psi, st = sp.full_solve(G, m, to_dev(src), tol=1e-10, inner=inner)
+    psi = to_host(psi)
+    ref, s0, _ = oracle.full_solve(dims, U, m, src, tol=1e-12, bc_t=bc_t)
+    res = np.linalg.norm(src - m * psi - oracle.dslash(dims, U, psi, bc_t=bc_t)) / np.linalg.norm(src)
+    err = rel_err_2(psi, ref)
+    announce(f"  iters={st.iters} err={err:.3e} full residual={res:.3e}")
+    assert st.converged and s0 == 0
+    assert err <= 1e-8
+    assert res <= 1e-9
+
+
+def test_full_system_solve_rejects_zero_mass():
+    dims = (4, 4, 4, 4)
+    G = gauge(dims, li.haar_links(dims, 503), "f32")
+    with pytest.raises(sp.StagError) as e:
+        sp.full_solve(G, 0.0, to_dev(li.gaussian_vector(256, 504)))
+    assert e.value.code == -1
