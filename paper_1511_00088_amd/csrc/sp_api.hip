@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <chrono>
 #include <climits>
 #include <cmath>
@@ -159,7 +160,7 @@ struct GroupPlan {
     const sp_gauge* U;
     std::vector<int> sys;  // indices into the caller's system list
     int nblk = 0, blk0 = 0;
-    size_t partials_off = 0, partials_p_off = 0;
+    size_t partials_off = 0, partials_p_off = 0, partials_r_off = 0;
 };
 
 struct Layout {
@@ -254,6 +255,8 @@ int make_layout(int nsys, const sp_system* systems, const sp_cg_params* prm, int
         off += align256(sizeof(double) * (size_t)(2 * NB) * blocks_for(G.g.Vh, 64));
         G.partials_p_off = off;
         off += align256(sizeof(double) * (size_t)NB * blocks_for(G.g.Vh, 64));
+        G.partials_r_off = off;
+        off += align256(sizeof(double) * (size_t)blocks_for(G.g.Vh, 64));
     }
     L->sys_off.assign(nsys, 0);
     L->sys_group.assign(nsys, 0);
@@ -286,6 +289,13 @@ struct Plan {
     LaunchCfg cfg;
 };
 
+// One system with at most four partials per thread: every block of the update forms alpha itself, which
+// saves the alpha finalize launch (k_dslash, DS_UPDATE_FUSED).
+template <class D>
+bool fused_alpha(const Plan& pl) {
+    return std::is_same<D, DescSingle>::value && pl.nblocks <= 4 * pl.cfg.nt;
+}
+
 // One CG iteration: t = D_oe p (|t|^2) -> alpha -> x += alpha p, r -= alpha (m^2 p - D_eo t) (|r|^2) -> beta
 // and triggers -> p = r + beta p (|p|^2).
 template <class D>
@@ -296,11 +306,20 @@ hipError_t enqueue_iterations(const D& d, const Plan& pl, int count, hipStream_t
         if ((e = launch_dslash(d, pl.nblocks, pl.cfg, pl.lp, pl.recon, pl.inner, 1, S_P, S_T, DS_NORM, G_ITER, use64,
                                s)))
             return e;
-        if ((e = launch_finalize(d, pl.ngroups, FIN_ALPHA, G_ITER, s))) return e;
-        if ((e = launch_dslash(d, pl.nblocks, pl.cfg, pl.lp, pl.recon, pl.inner, 0, S_T, S_R, DS_UPDATE, G_ITER,
-                               use64, s)))
-            return e;
-        if ((e = launch_finalize(d, pl.ngroups, i + 1 == count ? FIN_UPDATE_END : FIN_UPDATE, G_ITER, s))) return e;
+        const bool end = i + 1 == count;
+        if (fused_alpha<D>(pl)) {
+            if ((e = launch_dslash(d, pl.nblocks, pl.cfg, pl.lp, pl.recon, pl.inner, 0, S_T, S_R, DS_UPDATE_FUSED,
+                                   G_ITER, use64, s)))
+                return e;
+            if ((e = launch_finalize(d, pl.ngroups, end ? FIN_UPDATE_FUSED_END : FIN_UPDATE_FUSED, G_ITER, s)))
+                return e;
+        } else {
+            if ((e = launch_finalize(d, pl.ngroups, FIN_ALPHA, G_ITER, s))) return e;
+            if ((e = launch_dslash(d, pl.nblocks, pl.cfg, pl.lp, pl.recon, pl.inner, 0, S_T, S_R, DS_UPDATE, G_ITER,
+                                   use64, s)))
+                return e;
+            if ((e = launch_finalize(d, pl.ngroups, end ? FIN_UPDATE_END : FIN_UPDATE, G_ITER, s))) return e;
+        }
         if ((e = launch_xpay(d, pl.nblocks, pl.cfg, pl.inner, G_ITER, s))) return e;
     }
     return hipSuccess;
@@ -469,6 +488,7 @@ int solve_impl(int nsys, const sp_system* systems, const sp_cg_params* prm, sp_c
         gd.links_lo = prm->inner == SP_F64 ? G.U->f64 : G.U->lo;
         gd.partials = (double*)(base + G.partials_off);
         gd.partials_p = (double*)(base + G.partials_p_off);
+        gd.partials_r = (double*)(base + G.partials_r_off);
         gd.nrhs = (int)G.sys.size();
         gd.sys0 = sys_counter;
         gd.blk0 = G.blk0;

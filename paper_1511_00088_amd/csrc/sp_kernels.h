@@ -41,6 +41,7 @@ struct GroupDev {
     const void* links64;
     double* partials;   // [nblk][2 N] block partials of the last reducing launch
     double* partials_p; // [nblk][N]   block partials of |p|^2 from the last p update
+    double* partials_r; // [nblk]      block partials of |r|^2 from DS_UPDATE_FUSED
     int nrhs, sys0, blk0, nblk;
 };
 
@@ -111,13 +112,13 @@ __device__ __forceinline__ Rhs<N> rhs_of(const D& d, const GroupDev& G, int gate
     return h;
 }
 
-// First reduction stage: block totals of NV values per thread, stored by thread 0 as partials[gblk][NV].
+// First reduction stage: block totals of NV values per thread, stored by thread 0 as dst[gblk][NV].
 template <int NV>
-__device__ __forceinline__ void block_partials(const GroupDev& G, int gblk, double (&v)[NV]) {
+__device__ __forceinline__ void block_partials(double* dst, int gblk, double (&v)[NV]) {
     block_sum<NV>(v);
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int k = 0; k < NV; ++k) G.partials[(size_t)gblk * NV + k] = v[k];
+        for (int k = 0; k < NV; ++k) dst[(size_t)gblk * NV + k] = v[k];
     }
 }
 
@@ -127,8 +128,12 @@ __device__ __forceinline__ void block_partials(const GroupDev& G, int gblk, doub
 //   DS_NORM  : t = D_oe p (out), block partials of Re<t, t_stored>; with |p|^2 from the last p update this
 //              gives Re<p, A p> = m^2 |p|^2 + |D_oe p|^2 and alpha, since D_eo = -D_oe^dag for any links
 //   DS_UPDATE: q = m^2 p - D_eo t (not stored); x += alpha p; r -= alpha q; block partials of |r|^2
+//   DS_UPDATE_FUSED (one system): as DS_UPDATE, but every block forms alpha itself from the partials of
+//              |D_oe p|^2 and |p|^2 (summed in the same order in every block, so all blocks agree bit for
+//              bit); the loads are issued before the gather and used after it. Saves the alpha finalize
+//              launch when the partials are few; |r|^2 partials go to partials_r.
 // ------------------------------------------------------------------------------------------------------
-enum DsMode : int { DS_PLAIN = 0, DS_NORM = 1, DS_UPDATE = 2 };
+enum DsMode : int { DS_PLAIN = 0, DS_NORM = 1, DS_UPDATE = 2, DS_UPDATE_FUSED = 3 };
 
 // Multi-system launches keep every load unconditional so that the compiler can keep all of them in flight:
 // right-hand sides beyond the group's count read the last system's vectors and store nothing, and systems
@@ -159,12 +164,22 @@ __global__ __launch_bounds__(256) void k_dslash(D d, int p, int in_slot, int out
     double dots[N];
 #pragma unroll
     for (int r = 0; r < N; ++r) dots[r] = 0.0;
-
-    if (cb < g.Vh) {
-        const Site s = site_of(g, p, cb);
-        Vec3<R> acc[N];
+    constexpr bool FUSED = MODE == DS_UPDATE_FUSED;
+    static_assert(!FUSED || N == 1, "alpha is formed in-block for one system only");
+    double pre[2] = {0.0, 0.0};  // FUSED: this thread's share of the |D_oe p|^2 and |p|^2 partials
+    if constexpr (FUSED) {
+        for (int b = threadIdx.x; b < G.nblk; b += blockDim.x) {
+            pre[0] += G.partials[b];
+            pre[1] += G.partials_p[b];
+        }
+    }
+    const bool live = cb < g.Vh;
+    Vec3<R> acc[N];
 #pragma unroll
-        for (int r = 0; r < N; ++r) acc[r] = vzero<R>();
+    for (int r = 0; r < N; ++r) acc[r] = vzero<R>();
+
+    if (live) {
+        const Site s = site_of(g, p, cb);
 // one direction at a time for several systems (their gathers would not fit in registers otherwise)
 #pragma unroll(N == 1 ? 4 : 1)
         for (int mu = 0; mu < 4; ++mu) {
@@ -195,6 +210,20 @@ __global__ __launch_bounds__(256) void k_dslash(D d, int p, int in_slot, int out
                 acc[r].c[i].re *= R(0.5);
                 acc[r].c[i].im *= R(0.5);
             }
+    }
+    R alpha_blk = R(0);
+    if constexpr (FUSED) {
+        __shared__ double a_sh;
+        block_sum<2>(pre);
+        if (threadIdx.x == 0) {
+            const SolverState* st = h.st[0];
+            const double pq = st->m2 * pre[1] + pre[0];
+            a_sh = (pq > 0.0 && isfinite(pq)) ? st->rho / pq : 0.0;  // breakdown: no update, flagged later
+        }
+        __syncthreads();
+        alpha_blk = (R)a_sh;
+    }
+    if (live) {
         if constexpr (MODE == DS_PLAIN) {
 #pragma unroll
             for (int r = 0; r < N; ++r)
@@ -229,7 +258,7 @@ __global__ __launch_bounds__(256) void k_dslash(D d, int p, int in_slot, int out
                 for (int j = 0; j < NG; ++j) {
                     const int r = r0 + j;
                     const R m2 = h.act[r] ? (R)h.st[r]->m2 : R(0);
-                    const R a = h.act[r] ? (R)h.st[r]->alpha : R(0);
+                    const R a = h.act[r] ? (FUSED ? alpha_blk : (R)h.st[r]->alpha) : R(0);
 #pragma unroll
                     for (int i = 0; i < 3; ++i) {
                         const R qre = m2 * pc[j].c[i].re - acc[r].c[i].re;
@@ -256,7 +285,8 @@ __global__ __launch_bounds__(256) void k_dslash(D d, int p, int in_slot, int out
             }
         }
     }
-    if constexpr (MODE != DS_PLAIN) block_partials<N>(G, gblk, dots);
+    if constexpr (MODE == DS_UPDATE_FUSED) block_partials<N>(G.partials_r, gblk, dots);
+    else if constexpr (MODE != DS_PLAIN) block_partials<N>(G.partials, gblk, dots);
 }
 
 // ------------------------------------------------------------------------------------------------------
@@ -331,7 +361,7 @@ __global__ __launch_bounds__(256) void k_resid(D d, int init, int remap) {
             VO::store(S.v[S_R], g.Vh, cb, ro);
         }
     }
-    block_partials<2 * N>(G, gblk, dots);
+    block_partials<2 * N>(G.partials, gblk, dots);
 }
 
 // p = r + beta p inside an iteration (gate G_ITER); p = a r + beta p after a reliable update or at the
@@ -439,7 +469,7 @@ __global__ __launch_bounds__(256) void k_norm_b(D d, int remap) {
 #pragma unroll
         for (int i = 0; i < 3; ++i) dots[r] += b.c[i].re * b.c[i].re + b.c[i].im * b.c[i].im;
     }
-    block_partials<N>(G, gblk, dots);
+    block_partials<N>(G.partials, gblk, dots);
 }
 
 // ------------------------------------------------------------------------------------------------------
@@ -453,6 +483,8 @@ enum FinKind : int {
     FIN_RESID_INIT = 3,
     FIN_NORM_B = 4,
     FIN_UPDATE_END = 5,  // last iteration of a chunk: also the delta and ru_every triggers
+    FIN_UPDATE_FUSED = 6,      // after DS_UPDATE_FUSED: record alpha / breakdown, then as FIN_UPDATE
+    FIN_UPDATE_FUSED_END = 7,  // ... on the last iteration of a chunk
 };
 
 // partials of FIN_ALPHA: |D_oe p|^2 (from DS_NORM) and |p|^2 (from k_xpay)
@@ -466,23 +498,34 @@ __global__ __launch_bounds__(1024) void k_finalize(D d, int kind, int gate) {
     if (!h.any) return;
     const bool two = kind == FIN_RESID || kind == FIN_RESID_INIT;
     const int nv = two ? 2 * N : N;
-    // s[0..nv) from partials; for FIN_ALPHA s[N..2N) holds the |p|^2 partials
-    double s[2 * N];
+    // s[0..nv) from partials; for FIN_ALPHA s[N..2N) holds the |p|^2 partials; for the fused update
+    // s[0..N) = |r|^2 (partials_r), s[N..2N) = |D_oe p|^2, s[2N..3N) = |p|^2
+    const bool fused = kind == FIN_UPDATE_FUSED || kind == FIN_UPDATE_FUSED_END;
+    double s[3 * N];
 #pragma unroll
-    for (int k = 0; k < 2 * N; ++k) s[k] = 0.0;
+    for (int k = 0; k < 3 * N; ++k) s[k] = 0.0;
     for (int b = threadIdx.x; b < G.nblk; b += blockDim.x) {
+        if (fused) {
+#pragma unroll
+            for (int k = 0; k < N; ++k) {
+                s[k] += G.partials_r[(size_t)b * N + k];
+                s[N + k] += G.partials[(size_t)b * N + k];
+                s[2 * N + k] += G.partials_p[(size_t)b * N + k];
+            }
+            continue;
+        }
 #pragma unroll
         for (int k = 0; k < 2 * N; ++k) {
             if (k < nv) s[k] += G.partials[(size_t)b * nv + k];
             else if (kind == FIN_ALPHA) s[k] += G.partials_p[(size_t)b * N + (k - N)];
         }
     }
-    block_sum<2 * N>(s);
+    block_sum<3 * N>(s);
     // thread r updates system r (the states are independent, their loads overlap)
-    __shared__ double tot[2 * N];
+    __shared__ double tot[3 * N];
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int k = 0; k < 2 * N; ++k) tot[k] = s[k];
+        for (int k = 0; k < 3 * N; ++k) tot[k] = s[k];
     }
     __syncthreads();
     const int r = threadIdx.x;
@@ -496,7 +539,11 @@ __global__ __launch_bounds__(1024) void k_finalize(D d, int kind, int gate) {
             st = h.st[q];
         }
     if (!act) return;
-    if (kind == FIN_ALPHA) fin_alpha(st, st->m2 * tot[N + r] + tot[r]);
+    if (fused) {
+        fin_alpha(st, st->m2 * tot[2 * N + r] + tot[N + r]);
+        if (!(st->flags & ST_DONE)) fin_update(st, tot[r], kind == FIN_UPDATE_FUSED_END);
+    } else if (kind == FIN_ALPHA)
+        fin_alpha(st, st->m2 * tot[N + r] + tot[r]);
     else if (kind == FIN_UPDATE || kind == FIN_UPDATE_END) fin_update(st, tot[r], kind == FIN_UPDATE_END);
     else if (kind == FIN_NORM_B) {
         st->bnorm2 = tot[r];

@@ -24,9 +24,14 @@ hipError_t launch_dslash(const D& d, int nblocks, LaunchCfg c, int lp, int recon
         else if (mode == DS_NORM)                                                                          \
             hipLaunchKernelGGL((k_dslash<LP, RC, VP, N, D, DS_NORM>), dim3(nblocks), dim3(c.nt), 0, s, d, p, \
                                in_slot, out_slot, gate, use64, c.remap);                                  \
-        else                                                                                               \
+        else if (mode == DS_UPDATE)                                                                        \
             hipLaunchKernelGGL((k_dslash<LP, RC, VP, N, D, DS_UPDATE>), dim3(nblocks), dim3(c.nt), 0, s, d, \
                                p, in_slot, out_slot, gate, use64, c.remap);                               \
+        else if constexpr (N == 1)                                                                         \
+            hipLaunchKernelGGL((k_dslash<LP, RC, VP, N, D, DS_UPDATE_FUSED>), dim3(nblocks), dim3(c.nt), 0, s, \
+                               d, p, in_slot, out_slot, gate, use64, c.remap);                            \
+        else                                                                                               \
+            return hipErrorInvalidValue;                                                                   \
         return hipGetLastError();                                                                          \
     } while (0)
     if (lp == F64 && recon == 18 && vp == F64) SP_LAUNCH(F64, 18, F64);
