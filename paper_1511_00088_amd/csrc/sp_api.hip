@@ -160,7 +160,7 @@ struct GroupPlan {
     const sp_gauge* U;
     std::vector<int> sys;  // indices into the caller's system list
     int nblk = 0, blk0 = 0;
-    size_t partials_off = 0, partials_p_off = 0, partials_r_off = 0;
+    size_t partials_off = 0, partials_p_off = 0, partials_r_off = 0, rec_off = 0;
 };
 
 struct Layout {
@@ -242,8 +242,9 @@ int make_layout(int nsys, const sp_system* systems, const sp_cg_params* prm, int
     L->total_blocks = blk;
     // control block: states, descriptors
     size_t off = 0;
+    // states: nsys current ones, then nsys spares (the second buffer of the fused single-system iteration)
     L->states_off = off;
-    off += align256(sizeof(SolverState) * nsys);
+    off += align256(sizeof(SolverState) * 2 * nsys);
     L->gdesc_off = off;
     off += align256(sizeof(GroupDev) * L->groups.size());
     L->sdesc_off = off;
@@ -257,6 +258,8 @@ int make_layout(int nsys, const sp_system* systems, const sp_cg_params* prm, int
         off += align256(sizeof(double) * (size_t)NB * blocks_for(G.g.Vh, 64));
         G.partials_r_off = off;
         off += align256(sizeof(double) * (size_t)blocks_for(G.g.Vh, 64));
+        G.rec_off = off;
+        off += align256(sizeof(double) * 2);
     }
     L->sys_off.assign(nsys, 0);
     L->sys_group.assign(nsys, 0);
@@ -289,10 +292,11 @@ struct Plan {
     LaunchCfg cfg;
 };
 
-// One system with at most four partials per thread: every block of the update forms alpha itself, which
-// saves the alpha finalize launch (k_dslash, DS_UPDATE_FUSED).
+// One system with at most four partials per thread: every block of the update forms alpha itself and
+// every block of the p update forms beta and the stopping decisions itself, so an iteration is three
+// launches with no finalize (k_dslash DS_UPDATE_FUSED, k_xpay_fused).
 template <class D>
-bool fused_alpha(const Plan& pl) {
+bool fused_single(const Plan& pl) {
     return std::is_same<D, DescSingle>::value && pl.nblocks <= 4 * pl.cfg.nt;
 }
 
@@ -306,22 +310,36 @@ hipError_t enqueue_iterations(const D& d, const Plan& pl, int count, hipStream_t
         if ((e = launch_dslash(d, pl.nblocks, pl.cfg, pl.lp, pl.recon, pl.inner, 1, S_P, S_T, DS_NORM, G_ITER, use64,
                                s)))
             return e;
-        const bool end = i + 1 == count;
-        if (fused_alpha<D>(pl)) {
-            if ((e = launch_dslash(d, pl.nblocks, pl.cfg, pl.lp, pl.recon, pl.inner, 0, S_T, S_R, DS_UPDATE_FUSED,
-                                   G_ITER, use64, s)))
-                return e;
-            if ((e = launch_finalize(d, pl.ngroups, end ? FIN_UPDATE_FUSED_END : FIN_UPDATE_FUSED, G_ITER, s)))
-                return e;
-        } else {
-            if ((e = launch_finalize(d, pl.ngroups, FIN_ALPHA, G_ITER, s))) return e;
-            if ((e = launch_dslash(d, pl.nblocks, pl.cfg, pl.lp, pl.recon, pl.inner, 0, S_T, S_R, DS_UPDATE, G_ITER,
-                                   use64, s)))
-                return e;
-            if ((e = launch_finalize(d, pl.ngroups, end ? FIN_UPDATE_END : FIN_UPDATE, G_ITER, s))) return e;
-        }
+        if ((e = launch_finalize(d, pl.ngroups, FIN_ALPHA, G_ITER, s))) return e;
+        if ((e = launch_dslash(d, pl.nblocks, pl.cfg, pl.lp, pl.recon, pl.inner, 0, S_T, S_R, DS_UPDATE, G_ITER,
+                               use64, s)))
+            return e;
+        if ((e = launch_finalize(d, pl.ngroups, i + 1 == count ? FIN_UPDATE_END : FIN_UPDATE, G_ITER, s))) return e;
         if ((e = launch_xpay(d, pl.nblocks, pl.cfg, pl.inner, G_ITER, s))) return e;
     }
+    return hipSuccess;
+}
+
+// The fused single-system iteration. Iteration i reads state buffer i % 2 (the descriptor's state and the
+// spare right after it) and writes the other; an odd count ends with a copy back, so that between chunks
+// the state is always in the descriptor's buffer.
+hipError_t enqueue_iterations_fused(const DescSingle& d0, const Plan& pl, int count, hipStream_t s) {
+    const int use64 = pl.inner == SP_F64;
+    DescSingle d[2] = {d0, d0};
+    d[1].sys.st = d0.sys.st + 1;
+    for (int i = 0; i < count; ++i) {
+        const DescSingle& di = d[i & 1];
+        hipError_t e;
+        if ((e = launch_dslash(di, pl.nblocks, pl.cfg, pl.lp, pl.recon, pl.inner, 1, S_P, S_T, DS_NORM, G_ITER,
+                               use64, s)))
+            return e;
+        if ((e = launch_dslash(di, pl.nblocks, pl.cfg, pl.lp, pl.recon, pl.inner, 0, S_T, S_R, DS_UPDATE_FUSED,
+                               G_ITER, use64, s)))
+            return e;
+        if ((e = launch_xpay_fused(di, d[(i + 1) & 1].sys.st, i + 1 == count, pl.nblocks, pl.cfg, pl.inner, s)))
+            return e;
+    }
+    if (count & 1) return launch_state_copy(d[1].sys.st, d[0].sys.st, s);
     return hipSuccess;
 }
 
@@ -353,7 +371,11 @@ hipError_t enqueue_setup(const D& d, const Plan& pl, hipStream_t s) {
 
 template <class D>
 hipError_t enqueue_chunk(const D& d, const Plan& pl, int iters, hipStream_t s) {
-    hipError_t e = enqueue_iterations(d, pl, iters, s);
+    hipError_t e;
+    if constexpr (std::is_same<D, DescSingle>::value)
+        e = fused_single<D>(pl) ? enqueue_iterations_fused(d, pl, iters, s) : enqueue_iterations(d, pl, iters, s);
+    else
+        e = enqueue_iterations(d, pl, iters, s);
     if (e) return e;
     return enqueue_reliable(d, pl, s);
 }
@@ -489,6 +511,7 @@ int solve_impl(int nsys, const sp_system* systems, const sp_cg_params* prm, sp_c
         gd.partials = (double*)(base + G.partials_off);
         gd.partials_p = (double*)(base + G.partials_p_off);
         gd.partials_r = (double*)(base + G.partials_r_off);
+        gd.rec = (double*)(base + G.rec_off);
         gd.nrhs = (int)G.sys.size();
         gd.sys0 = sys_counter;
         gd.blk0 = G.blk0;

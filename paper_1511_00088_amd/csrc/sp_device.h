@@ -493,9 +493,9 @@ __device__ __forceinline__ void block_sum(double (&v)[NV]) {
 }
 
 // ------------------------------------------------------------------------------------------------------
-// Device-resident CG state of one system. Written only by the last block of a reducing kernel (after
-// every block of that launch has read it) and read by later launches, so every block of a launch sees
-// the same values.
+// Device-resident CG state of one system. Written by the one-block finalize launch, or, in the fused
+// single-system iteration, by block 0 into a second buffer that only later launches read; either way every
+// block of a launch sees the same values.
 // ------------------------------------------------------------------------------------------------------
 enum : int {
     ST_DONE = 1,        // stop: every kernel of this system returns at entry

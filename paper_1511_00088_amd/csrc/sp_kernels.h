@@ -42,6 +42,7 @@ struct GroupDev {
     double* partials;   // [nblk][2 N] block partials of the last reducing launch
     double* partials_p; // [nblk][N]   block partials of |p|^2 from the last p update
     double* partials_r; // [nblk]      block partials of |r|^2 from DS_UPDATE_FUSED
+    double* rec;        // [2]         Re<p,Ap> and alpha of the last DS_UPDATE_FUSED (block 0 writes them)
     int nrhs, sys0, blk0, nblk;
 };
 
@@ -131,7 +132,8 @@ __device__ __forceinline__ void block_partials(double* dst, int gblk, double (&v
 //   DS_UPDATE_FUSED (one system): as DS_UPDATE, but every block forms alpha itself from the partials of
 //              |D_oe p|^2 and |p|^2 (summed in the same order in every block, so all blocks agree bit for
 //              bit); the loads are issued before the gather and used after it. Saves the alpha finalize
-//              launch when the partials are few; |r|^2 partials go to partials_r.
+//              launch when the partials are few; |r|^2 partials go to partials_r, Re<p,Ap> and alpha to
+//              rec for k_xpay_fused, which takes the place of the update finalize.
 // ------------------------------------------------------------------------------------------------------
 enum DsMode : int { DS_PLAIN = 0, DS_NORM = 1, DS_UPDATE = 2, DS_UPDATE_FUSED = 3 };
 
@@ -219,6 +221,10 @@ __global__ __launch_bounds__(256) void k_dslash(D d, int p, int in_slot, int out
             const SolverState* st = h.st[0];
             const double pq = st->m2 * pre[1] + pre[0];
             a_sh = (pq > 0.0 && isfinite(pq)) ? st->rho / pq : 0.0;  // breakdown: no update, flagged later
+            if (gblk == 0) {
+                G.rec[0] = pq;
+                G.rec[1] = a_sh;
+            }
         }
         __syncthreads();
         alpha_blk = (R)a_sh;
@@ -421,6 +427,63 @@ __global__ __launch_bounds__(256) void k_xpay(D d, int gate, int remap) {
     }
 }
 
+// One system, after DS_UPDATE_FUSED: every block sums the |r|^2 partials (same order in every block) and
+// takes the decisions of the update finalize itself (breakdown, convergence and reliable-update triggers,
+// beta), then p = r + beta p with |p|^2 partials. The state is double-buffered: all blocks read st_in
+// (the descriptor's state) and block 0 writes the advanced state to st_out, which the next iteration's
+// launches read, so no block can see a half-written state.
+template <int VP>
+__global__ __launch_bounds__(256) void k_xpay_fused(DescSingle d, SolverState* __restrict__ st_out, int chunk_end,
+                                                     int remap) {
+    using R = typename Real<VP>::T;
+    using VF = VecFmt<VP>;
+    const int gblk = logical_block(remap);
+    const GroupDev& G = d.grp;
+    const SolverState* st = d.sys.st;
+    const int Vh = G.g.Vh;
+    const int cb = gblk * blockDim.x + threadIdx.x;
+    const bool live = cb < Vh;
+    // loads that do not depend on the state go first
+    double part[1] = {0.0};
+    for (int b = threadIdx.x; b < G.nblk; b += blockDim.x) part[0] += G.partials_r[b];
+    Vec3<R> rv = vzero<R>(), pv = vzero<R>();
+    if (live) {
+        rv = VF::load(d.sys.v[S_R], Vh, cb);
+        pv = VF::load(d.sys.v[S_P], Vh, cb);
+    }
+    block_sum<1>(part);
+    __shared__ double beta_sh;
+    __shared__ int go_sh;
+    if (threadIdx.x == 0) {
+        SolverState s = *st;
+        bool go = false;
+        if (!(s.flags & (ST_DONE | ST_PENDING))) {
+            fin_alpha(&s, G.rec[0]);
+            if (!(s.flags & ST_DONE)) fin_update(&s, part[0], chunk_end != 0);
+            go = !(s.flags & (ST_DONE | ST_PENDING));
+        }
+        if (gblk == 0) *st_out = s;
+        beta_sh = s.beta;
+        go_sh = go;
+    }
+    __syncthreads();
+    if (!go_sh) return;  // paused or stopped: p and its partials stay as they are
+    const R beta = (R)beta_sh;
+    double dots[1] = {0.0};
+    if (live) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            pv.c[i].re = rv.c[i].re + beta * pv.c[i].re;
+            pv.c[i].im = rv.c[i].im + beta * pv.c[i].im;
+        }
+        const Vec3<R> ps = VF::store_rt(d.sys.v[S_P], Vh, cb, pv);
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+            dots[0] += (double)ps.c[i].re * (double)ps.c[i].re + (double)ps.c[i].im * (double)ps.c[i].im;
+    }
+    block_partials<1>(G.partials_p, gblk, dots);
+}
+
 // x64 += xlo; xlo = 0 (reliable update).
 template <int N, class D>
 __global__ __launch_bounds__(256) void k_accum(D d, int remap) {
@@ -483,8 +546,6 @@ enum FinKind : int {
     FIN_RESID_INIT = 3,
     FIN_NORM_B = 4,
     FIN_UPDATE_END = 5,  // last iteration of a chunk: also the delta and ru_every triggers
-    FIN_UPDATE_FUSED = 6,      // after DS_UPDATE_FUSED: record alpha / breakdown, then as FIN_UPDATE
-    FIN_UPDATE_FUSED_END = 7,  // ... on the last iteration of a chunk
 };
 
 // partials of FIN_ALPHA: |D_oe p|^2 (from DS_NORM) and |p|^2 (from k_xpay)
@@ -498,34 +559,23 @@ __global__ __launch_bounds__(1024) void k_finalize(D d, int kind, int gate) {
     if (!h.any) return;
     const bool two = kind == FIN_RESID || kind == FIN_RESID_INIT;
     const int nv = two ? 2 * N : N;
-    // s[0..nv) from partials; for FIN_ALPHA s[N..2N) holds the |p|^2 partials; for the fused update
-    // s[0..N) = |r|^2 (partials_r), s[N..2N) = |D_oe p|^2, s[2N..3N) = |p|^2
-    const bool fused = kind == FIN_UPDATE_FUSED || kind == FIN_UPDATE_FUSED_END;
-    double s[3 * N];
+    // s[0..nv) from partials; for FIN_ALPHA s[N..2N) holds the |p|^2 partials
+    double s[2 * N];
 #pragma unroll
-    for (int k = 0; k < 3 * N; ++k) s[k] = 0.0;
+    for (int k = 0; k < 2 * N; ++k) s[k] = 0.0;
     for (int b = threadIdx.x; b < G.nblk; b += blockDim.x) {
-        if (fused) {
-#pragma unroll
-            for (int k = 0; k < N; ++k) {
-                s[k] += G.partials_r[(size_t)b * N + k];
-                s[N + k] += G.partials[(size_t)b * N + k];
-                s[2 * N + k] += G.partials_p[(size_t)b * N + k];
-            }
-            continue;
-        }
 #pragma unroll
         for (int k = 0; k < 2 * N; ++k) {
             if (k < nv) s[k] += G.partials[(size_t)b * nv + k];
             else if (kind == FIN_ALPHA) s[k] += G.partials_p[(size_t)b * N + (k - N)];
         }
     }
-    block_sum<3 * N>(s);
+    block_sum<2 * N>(s);
     // thread r updates system r (the states are independent, their loads overlap)
-    __shared__ double tot[3 * N];
+    __shared__ double tot[2 * N];
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int k = 0; k < 3 * N; ++k) tot[k] = s[k];
+        for (int k = 0; k < 2 * N; ++k) tot[k] = s[k];
     }
     __syncthreads();
     const int r = threadIdx.x;
@@ -539,11 +589,7 @@ __global__ __launch_bounds__(1024) void k_finalize(D d, int kind, int gate) {
             st = h.st[q];
         }
     if (!act) return;
-    if (fused) {
-        fin_alpha(st, st->m2 * tot[2 * N + r] + tot[N + r]);
-        if (!(st->flags & ST_DONE)) fin_update(st, tot[r], kind == FIN_UPDATE_FUSED_END);
-    } else if (kind == FIN_ALPHA)
-        fin_alpha(st, st->m2 * tot[N + r] + tot[r]);
+    if (kind == FIN_ALPHA) fin_alpha(st, st->m2 * tot[N + r] + tot[r]);
     else if (kind == FIN_UPDATE || kind == FIN_UPDATE_END) fin_update(st, tot[r], kind == FIN_UPDATE_END);
     else if (kind == FIN_NORM_B) {
         st->bnorm2 = tot[r];

@@ -30,6 +30,10 @@ template <class D>
 hipError_t launch_accum(const D& d, int nblocks, LaunchCfg c, hipStream_t s);
 template <class D>
 hipError_t launch_norm_b(const D& d, int nblocks, LaunchCfg c, hipStream_t s);
+// Fused p update of one system (k_xpay_fused): reads d's state, writes the advanced state to st_out.
+hipError_t launch_xpay_fused(const DescSingle& d, SolverState* st_out, int chunk_end, int nblocks, LaunchCfg c, int vp,
+                             hipStream_t s);
+hipError_t launch_state_copy(const SolverState* src, SolverState* dst, hipStream_t s);
 // Second reduction stage (k_finalize), one block per group.
 template <class D>
 hipError_t launch_finalize(const D& d, int ngroups, int kind, int gate, hipStream_t s);

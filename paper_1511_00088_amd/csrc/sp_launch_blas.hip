@@ -9,6 +9,11 @@ __global__ __launch_bounds__(256) void k_zero16(uint4* p, long n) {
     if (i < n) p[i] = make_uint4(0u, 0u, 0u, 0u);
 }
 
+// *dst = *src for the double-buffered state of k_xpay_fused (one thread).
+__global__ void k_state_copy(const SolverState* __restrict__ src, SolverState* __restrict__ dst) {
+    if (threadIdx.x == 0) *dst = *src;
+}
+
 template <class D>
 struct NOf {
     static constexpr int value = NB;
@@ -32,6 +37,26 @@ hipError_t launch_xpay(const D& d, int nblocks, LaunchCfg c, int vp, int gate, h
     if (vp == BF16) SP_LAUNCH(BF16);
 #undef SP_LAUNCH
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_xpay_fused(const DescSingle& d, SolverState* st_out, int chunk_end, int nblocks, LaunchCfg c, int vp,
+                             hipStream_t s) {
+#define SP_LAUNCH(VP)                                                                                      \
+    do {                                                                                                   \
+        hipLaunchKernelGGL((k_xpay_fused<VP>), dim3(nblocks), dim3(c.nt), 0, s, d, st_out, chunk_end, c.remap); \
+        return hipGetLastError();                                                                          \
+    } while (0)
+    if (vp == F64) SP_LAUNCH(F64);
+    if (vp == F32) SP_LAUNCH(F32);
+    if (vp == F16) SP_LAUNCH(F16);
+    if (vp == BF16) SP_LAUNCH(BF16);
+#undef SP_LAUNCH
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_state_copy(const SolverState* src, SolverState* dst, hipStream_t s) {
+    hipLaunchKernelGGL(k_state_copy, dim3(1), dim3(64), 0, s, src, dst);
+    return hipGetLastError();
 }
 
 template <class D>
