@@ -232,6 +232,12 @@ int make_layout(int nsys, const sp_system* systems, const sp_cg_params* prm, int
         const int lp = prm->inner == SP_F64 ? SP_F64 : G.U->lo_prec;
         const int rc = prm->inner == SP_F64 ? 18 : G.U->recon;
         L->cfg = tuned_cfg(G.g, lp, rc, prm->inner);
+        // one system: 256-thread blocks when they admit the fused iteration and the tuned shape does not
+        // (the block size moves the operator by a few percent at most, the fused iteration saves a
+        // finalize launch per iteration)
+        if (n_rhs_max == 1 && blocks_for(G.g.Vh, L->cfg.nt) > FUSED_PARTIALS * L->cfg.nt &&
+            blocks_for(G.g.Vh, 256) <= FUSED_PARTIALS * 256)
+            L->cfg.nt = 256;
     }
     int blk = 0;
     for (auto& G : L->groups) {
@@ -297,7 +303,7 @@ struct Plan {
 // launches with no finalize (k_dslash DS_UPDATE_FUSED, k_xpay_fused).
 template <class D>
 bool fused_single(const Plan& pl) {
-    return std::is_same<D, DescSingle>::value && pl.nblocks <= 4 * pl.cfg.nt;
+    return std::is_same<D, DescSingle>::value && pl.nblocks <= FUSED_PARTIALS * pl.cfg.nt;
 }
 
 // One CG iteration: t = D_oe p (|t|^2) -> alpha -> x += alpha p, r -= alpha (m^2 p - D_eo t) (|r|^2) -> beta

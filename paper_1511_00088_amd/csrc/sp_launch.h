@@ -17,6 +17,9 @@ static constexpr int NB = 4;
 
 inline int blocks_for(int n, int nt) { return (n + nt - 1) / nt; }
 
+// The fused single-system iteration has every block sum all block partials: at most this many per thread.
+static constexpr int FUSED_PARTIALS = 4;
+
 // Half operator (see k_dslash; mode DS_PLAIN, DS_NORM or DS_UPDATE). D = DescSingle (one system) or
 // DescBatch (up to NB per group).
 template <class D>
