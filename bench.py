@@ -36,6 +36,80 @@ def dslash_bytes_per_site(prec, recon):
     return 8 * LINK_BYTES[(prec, recon)] + 2 * VEC_BYTES[prec]
 
 
+def iteration_bytes_per_site(prec, recon):
+    """Algorithmic bytes per even site of one mixed-precision CG iteration: t = D_oe p (links, p, t);
+    x += alpha p, r -= alpha (m^2 p - D_eo t) (links, t, p, x and r read and written; x in FP32 for
+    every inner precision); p = r + beta p (r, p read, p written)."""
+    links, v, x = 8 * LINK_BYTES[(prec, recon)], VEC_BYTES[prec], VEC_BYTES["f32"]
+    return (links + 2 * v) + (links + 2 * v + 2 * x + 2 * v) + 3 * v
+
+
+def control_links(dims, eps, seed, dev, torch):
+    """Near-identity SU(3) links exp(i eps H), H = sum_a h_a lambda_a / 2, generated on the GPU with a
+    seeded torch generator: the control lattice only measures bandwidth and is too large for the host
+    generator to be quick. [4][V][3][3] complex128."""
+    import lattice_inputs as li
+
+    V = dims[0] * dims[1] * dims[2] * dims[3]
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(seed)
+    lam = torch.from_numpy((li.gell_mann() / 2.0).reshape(8, 9)).to(dev)
+    out = torch.empty(4, V, 3, 3, dtype=torch.complex128, device=dev)
+    chunk = 1 << 20
+    for mu in range(4):
+        for s in range(0, V, chunk):
+            n = min(chunk, V - s)
+            h = torch.randn(n, 8, generator=gen, device=dev, dtype=torch.float64).to(torch.complex128)
+            out[mu, s:s + n] = torch.linalg.matrix_exp((1j * eps) * (h @ lam).reshape(n, 3, 3))
+    return out
+
+
+def time_dslash(sp, torch, G, prec, inp, out, reps, stream, flush=None):
+    """Mean time of one half-Dslash launch over `reps` back-to-back launches (HIP events on the launch
+    stream), or, with a flush buffer, the median over launches each timed alone after reading the buffer
+    (1 GiB of float32, four times the Infinity Cache; read, not written, so that the cache holds no dirty
+    lines whose write-back the launch would pay) so that links and vectors come from HBM. The
+    single-launch figure includes the event pair's own overhead (G = None measures that alone)."""
+    for _ in range(10 if G is not None else 0):
+        sp.dslash_packed(G, prec, inp, 1, out)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    if flush is None:
+        e0.record(stream)
+        for _ in range(reps):
+            sp.dslash_packed(G, prec, inp, 1, out)
+        e1.record(stream)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / 1e3 / reps
+    ts = []
+    for k in range(reps):
+        flush.sum()
+        e0.record(stream)
+        if G is not None:
+            sp.dslash_packed(G, prec, inp, 1, out)
+        e1.record(stream)
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1) / 1e3)
+    ts.sort()
+    return ts[len(ts) // 2]
+
+
+def copy_bandwidth(torch, dev, stream, n=1 << 30, reps=10):
+    """Device-to-device copy of n bytes: GB/s counting the read and the write."""
+    src = torch.ones(n, dtype=torch.uint8, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record(stream)
+    e1.synchronize()
+    return 2 * n * reps / (e0.elapsed_time(e1) / 1e3) / 1e9
+
+
 KERNEL_SOURCES = ["paper_1511_00088_amd/csrc/sp_device.h", "paper_1511_00088_amd/csrc/sp_kernels.h",
                   "paper_1511_00088_amd/csrc/sp_launch_dslash.hip", "paper_1511_00088_amd/tune_mi355x.json"]
 def traffic_file(prec, recon, dims):
@@ -251,32 +325,47 @@ def main():
     # --- dominant kernel: half-Dslash in the inner precision, HIP events on the launch stream ---
     inp = sp.pack_vec(lat, b, args.inner)
     out = torch.empty_like(inp)
-    for _ in range(20):
-        sp.dslash_packed(G, args.inner, inp, 1, out)
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(args.dslash_reps):
-        sp.dslash_packed(G, args.inner, inp, 1, out)
-    e1.record(stream)
-    e1.synchronize()
-    t_d = e0.elapsed_time(e1) / 1e3 / args.dslash_reps
+    t_d = time_dslash(sp, torch, G, args.inner, inp, out, args.dslash_reps, stream)
     bps = dslash_bytes_per_site(args.inner, args.recon)
     achieved = bps * lat.Vh / t_d / 1e9
     gflops = FLOP_PER_SITE * lat.Vh / t_d / 1e9
     # FP64 half-Dslash as well (the reliable-update and plain-FP64 kernel)
     inp64 = sp.pack_vec(lat, b, "f64")
     out64 = torch.empty_like(inp64)
-    for _ in range(10):
-        sp.dslash_packed(G64, "f64", inp64, 1, out64)
-    e0.record(stream)
-    for _ in range(args.dslash_reps // 2):
-        sp.dslash_packed(G64, "f64", inp64, 1, out64)
-    e1.record(stream)
-    e1.synchronize()
-    t_d64 = e0.elapsed_time(e1) / 1e3 / (args.dslash_reps // 2)
+    t_d64 = time_dslash(sp, torch, G64, "f64", inp64, out64, args.dslash_reps // 2, stream)
     log(f"dslash {args.inner} r{args.recon}: {t_d * 1e6:.2f} us, {achieved:.0f} GB/s, {gflops:.0f} GFLOP/s; "
         f"f64: {t_d64 * 1e6:.2f} us")
+    # the same launches with the Infinity Cache flushed before each, and a plain copy's bandwidth
+    flush = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+    t_df = time_dslash(sp, torch, G, args.inner, inp, out, 30, stream, flush)
+    t_ev = time_dslash(sp, torch, None, args.inner, inp, out, 30, stream, flush)
+    copy_gbs = copy_bandwidth(torch, dev, stream)
+    log(f"dslash flushed: {t_df * 1e6:.2f} us ({bps * lat.Vh / t_df / 1e9:.0f} GB/s); copy {copy_gbs:.0f} GB/s")
+    dslash_extra = {"flushed_us": t_df * 1e6, "event_pair_us": t_ev * 1e6, "flushed_hbm_frac": bps * lat.Vh / t_df / 1e9 / HBM_PEAK_GBS,
+                    "copy_GBs": copy_gbs, "frac_of_copy": achieved / copy_gbs,
+                    "flushed_frac_of_copy": bps * lat.Vh / t_df / 1e9 / copy_gbs}
+    if not args.no_extras:
+        # control lattice 32^3x64: links of every packing are more than the 256 MB Infinity Cache
+        cd = (32, 32, 32, 64)
+        clat = sp.Lattice(cd)
+        clinks = control_links(cd, 0.3, 51, dev, torch)
+        cv = torch.randn(clat.Vh, 3, dtype=torch.complex128, device=dev)
+        ctl = {}
+        for rc in (18, 12):
+            Gc = sp.Gauge(clat, clinks, lo_prec=args.inner, recon=rc)
+            ci = sp.pack_vec(clat, cv, args.inner)
+            co = torch.empty_like(ci)
+            cb = dslash_bytes_per_site(args.inner, rc)
+            tc = time_dslash(sp, torch, Gc, args.inner, ci, co, 100, stream)
+            tcf = time_dslash(sp, torch, Gc, args.inner, ci, co, 20, stream, flush)
+            ctl[f"{args.inner}_r{rc}"] = {"us": tc * 1e6, "hbm_frac": cb * clat.Vh / tc / 1e9 / HBM_PEAK_GBS,
+                                          "flushed_us": tcf * 1e6,
+                                          "flushed_hbm_frac": cb * clat.Vh / tcf / 1e9 / HBM_PEAK_GBS}
+            log(f"control 32^3x64 {args.inner} r{rc}: {tc * 1e6:.1f} us, flushed {tcf * 1e6:.1f} us")
+            del Gc, ci, co
+        del clinks
+        dslash_extra["control_32x32x32x64"] = ctl
+    del flush
 
     traffic = measured_traffic(args.inner, args.recon, dims)
 
@@ -322,6 +411,8 @@ def main():
                          f"host {cpu_model()}, {os.cpu_count()} logical CPUs"}
         log(f"CPU oracle: {per_iter * 1e3:.1f} ms/iteration -> {cpu['value']:.1f} s")
 
+    ibps = iteration_bytes_per_site(args.inner, args.recon)
+    t_it = t_mixed / max(st.iters, 1)
     line = {
         "metric": METRIC,
         "value": t_mixed,
@@ -346,7 +437,10 @@ def main():
         "solve_s_min": min(per) if per else None,
         "dslash": {"prec": args.inner, "recon": args.recon, "us": t_d * 1e6, "gflops": gflops,
                    "bytes_per_site": bps, "hbm_frac": achieved / HBM_PEAK_GBS, "f64_us": t_d64 * 1e6,
-                   "f64_gflops": FLOP_PER_SITE * lat.Vh / t_d64 / 1e9},
+                   "f64_gflops": FLOP_PER_SITE * lat.Vh / t_d64 / 1e9, **dslash_extra},
+        "iteration": {"bytes_per_site": ibps, "us": t_it * 1e6, "achieved_GBs": ibps * lat.Vh / t_it / 1e9,
+                      "hbm_frac": ibps * lat.Vh / t_it / 1e9 / HBM_PEAK_GBS,
+                      "note": "whole solve time / iterations (reliable updates, set-up and polling included)"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
         "cpu_baseline": cpu,
