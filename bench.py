@@ -44,6 +44,31 @@ def iteration_bytes_per_site(prec, recon):
     return (links + 2 * v) + (links + 2 * v + 2 * x + 2 * v) + 3 * v
 
 
+def mean_stderr(ts):
+    """Mean and standard error of the mean of a list of times."""
+    n = len(ts)
+    m = sum(ts) / n
+    if n < 2:
+        return m, None
+    return m, (sum((t - m) ** 2 for t in ts) / (n - 1) / n) ** 0.5
+
+
+def timed_solves(torch, fn, n):
+    """Wall time of each of n calls (each solve returns after its stream reaches the end)."""
+    ts, out = [], None
+    for _ in range(n):
+        t0 = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    return ts, out
+
+
+# flop per lattice site (both parities) of one CG iteration: two half-Dslash (570 per output site each, on
+# half the sites), m^2 p (12 per even site) and five vector updates or dots (12 per even site each)
+CG_FLOP_PER_SITE = 606
+
+
 def control_links(dims, eps, seed, dev, torch):
     """Near-identity SU(3) links exp(i eps H), H = sum_a h_a lambda_a / 2, generated on the GPU with a
     seeded torch generator: the control lattice only measures bandwidth and is too large for the host
@@ -293,13 +318,8 @@ def main():
         x, st = solve_mixed()
     torch.cuda.synchronize()
     log(f"timing {args.steps} mixed-precision solves")
-    t0 = time.perf_counter()
-    per = []
-    for _ in range(args.steps):
-        x, st = solve_mixed()
-        per.append(st.seconds)
-    torch.cuda.synchronize()
-    t_mixed = (time.perf_counter() - t0) / max(args.steps, 1)
+    per, (x, st) = timed_solves(torch, solve_mixed, max(args.steps, 1))
+    t_mixed, t_mixed_se = mean_stderr(per)
     assert st.converged, f"mixed solve did not converge: {st}"
     log(f"mixed: {t_mixed * 1e3:.2f} ms/solve iters={st.iters} ru={st.reliable_updates} "
         f"resid={st.true_rel_resid:.3e}")
@@ -308,17 +328,15 @@ def main():
     if not args.no_fp64:
         x64, st64 = solve_fp64()
         torch.cuda.synchronize()
-        n64 = max(1, args.steps // 2)
-        t0 = time.perf_counter()
-        for _ in range(n64):
-            x64, st64 = solve_fp64()
-        torch.cuda.synchronize()
-        t_fp64 = (time.perf_counter() - t0) / n64
+        per64, (x64, st64) = timed_solves(torch, solve_fp64, max(1, args.steps // 2))
+        t_fp64, t_fp64_se = mean_stderr(per64)
         xref, stref = solve_fp64(1e-12)
         err = float(torch.linalg.norm(x - xref) / torch.linalg.norm(xref))
         err64 = float(torch.linalg.norm(x64 - xref) / torch.linalg.norm(xref))
         log(f"fp64: {t_fp64 * 1e3:.2f} ms/solve iters={st64.iters}; mixed err vs 1e-12 FP64 solve {err:.3e}")
-        extra.update(fp64_cg_s=t_fp64, fp64_iters=st64.iters, speedup_vs_fp64=t_fp64 / t_mixed,
+        extra.update(fp64_cg_s=t_fp64, fp64_cg_s_stderr=t_fp64_se, fp64_solves=len(per64),
+                     fp64_cg_gflops=CG_FLOP_PER_SITE * lat.V * st64.iters / t_fp64 / 1e9,
+                     fp64_iters=st64.iters, speedup_vs_fp64=t_fp64 / t_mixed,
                      err_mixed_vs_fp64_1e12=err, err_fp64_vs_fp64_1e12=err64, ref_iters_1e12=stref.iters,
                      fp64_true_rel_resid=st64.true_rel_resid)
 
@@ -365,6 +383,36 @@ def main():
             del Gc, ci, co
         del clinks
         dslash_extra["control_32x32x32x64"] = ctl
+        # every packing at the workload shape, back-to-back (tuned launch of each)
+        allc = {}
+        for prec, rc in LINK_BYTES:
+            Ga = G64 if prec == "f64" else sp.Gauge(lat, G64_links(), lo_prec=prec, recon=rc)
+            ai = sp.pack_vec(lat, b, prec)
+            ao = torch.empty_like(ai)
+            ta = time_dslash(sp, torch, Ga, prec, ai, ao, 100, stream)
+            ab = dslash_bytes_per_site(prec, rc)
+            allc[f"{prec}_r{rc}"] = {"us": ta * 1e6, "bytes_per_site": ab, "gflops": FLOP_PER_SITE * lat.Vh / ta / 1e9,
+                                     "hbm_frac": ab * lat.Vh / ta / 1e9 / HBM_PEAK_GBS}
+            del Ga, ai, ao
+        dslash_extra["all_packings"] = allc
+        log("all packings: " + ", ".join(f"{kk} {vv['us']:.1f} us" for kk, vv in allc.items()))
+        # one GPU's share of the workload cut in t across 8 GPUs: 20^3x8, periodic in t (its own halo)
+        sd = (dims[0], dims[1], dims[2], max(2, dims[3] // 8))
+        slat = sp.Lattice(sd)
+        sl = control_links(sd, 0.3, 52, dev, torch)
+        sv = torch.randn(slat.Vh, 3, dtype=torch.complex128, device=dev)
+        Gs = sp.Gauge(slat, sl, lo_prec=args.inner, recon=args.recon)
+        si = sp.pack_vec(slat, sv, args.inner)
+        so = torch.empty_like(si)
+        ts_ = time_dslash(sp, torch, Gs, args.inner, si, so, 200, stream)
+        face = sd[0] * sd[1] * sd[2] // 2 * VEC_BYTES[args.inner]
+        dslash_extra["shard_share"] = {
+            "dims": list(sd), "us": ts_ * 1e6, "hbm_frac": bps * slat.Vh / ts_ / 1e9 / HBM_PEAK_GBS,
+            "face_bytes": face,
+            "note": "half-Dslash on 1/8 of the workload (t cut in 8), periodic t standing in for the halo; "
+                    "each cut exchanges one face of this size per direction per half-Dslash"}
+        log(f"shard share {sd}: {ts_ * 1e6:.2f} us")
+        del Gs, sl, si, so
     del flush
 
     traffic = measured_traffic(args.inner, args.recon, dims)
@@ -377,14 +425,12 @@ def main():
                 Gl = sp.Gauge(lat, G64_links(), lo_prec=prec, recon=rc)
                 sp.cg_solve(Gl, mass, b, tol=tol, inner=prec, workspace=ws)
                 torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                nrep = 3
-                for _ in range(nrep):
-                    xl, stl = sp.cg_solve(Gl, mass, b, tol=tol, inner=prec, workspace=ws)
-                torch.cuda.synchronize()
-                tl = (time.perf_counter() - t0) / nrep
+                pl, (xl, stl) = timed_solves(
+                    torch, lambda: sp.cg_solve(Gl, mass, b, tol=tol, inner=prec, workspace=ws), 5)
+                tl, tl_se = mean_stderr(pl)
                 el = float(torch.linalg.norm(xl - xref) / torch.linalg.norm(xref))
-                low[f"{prec}_r{rc}"] = {"s": tl, "iters": stl.iters, "reliable_updates": stl.reliable_updates,
+                low[f"{prec}_r{rc}"] = {"s": tl, "s_stderr": tl_se, "solves": len(pl), "iters": stl.iters,
+                                        "reliable_updates": stl.reliable_updates,
                                         "true_rel_resid": stl.true_rel_resid, "err_vs_fp64_1e12": el}
                 log(f"{prec} r{rc}: {tl * 1e3:.2f} ms/solve iters={stl.iters} err={el:.2e}")
                 del Gl
@@ -398,8 +444,11 @@ def main():
 
         oracle.build(force=False)
         n_it = 40
-        log(f"CPU oracle: {n_it} FP64 CG iterations on {dims}")
+        log(f"CPU oracle: half-Dslash and {n_it} FP64 CG iterations on {dims}")
         bh = c["source"]
+        t0 = time.perf_counter()
+        oracle.dslash_eo(dims, c["links"], bh, 1)
+        t_cpu_d = time.perf_counter() - t0
         t0 = time.perf_counter()
         _, status, it, _ = oracle.cg_solve(dims, c["links"], mass, bh, tol=1e-30, max_iter=n_it)
         t_cpu = time.perf_counter() - t0
@@ -408,7 +457,8 @@ def main():
         cpu = {"value": per_iter * iters_needed, "unit": "s", "cores": 1, "kind": "oracle",
                "sample": f"{n_it} FP64 CG iterations of the single-threaded oracle on {dims[0]}^3x{dims[3]} "
                          f"({t_cpu:.1f} s), scaled to the {iters_needed} iterations FP64 CG needs for 1e-8; "
-                         f"host {cpu_model()}, {os.cpu_count()} logical CPUs"}
+                         f"host {cpu_model()}, {os.cpu_count()} logical CPUs",
+               "dslash_s": t_cpu_d, "dslash_gflops": FLOP_PER_SITE * lat.Vh / t_cpu_d / 1e9}
         log(f"CPU oracle: {per_iter * 1e3:.1f} ms/iteration -> {cpu['value']:.1f} s")
 
     ibps = iteration_bytes_per_site(args.inner, args.recon)
@@ -421,6 +471,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": t_mixed * 1e3,
+        "value_stderr": t_mixed_se,
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
@@ -435,6 +486,7 @@ def main():
         "reliable_updates": st.reliable_updates,
         "true_rel_resid": st.true_rel_resid,
         "solve_s_min": min(per) if per else None,
+        "cg_gflops": CG_FLOP_PER_SITE * lat.V * st.iters / t_mixed / 1e9,
         "dslash": {"prec": args.inner, "recon": args.recon, "us": t_d * 1e6, "gflops": gflops,
                    "bytes_per_site": bps, "hbm_frac": achieved / HBM_PEAK_GBS, "f64_us": t_d64 * 1e6,
                    "f64_gflops": FLOP_PER_SITE * lat.Vh / t_d64 / 1e9, **dslash_extra},
