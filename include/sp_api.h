@@ -185,6 +185,27 @@ int sp_cg_force(const sp_geom* g, const sp_gauge* U, double mass, const double* 
                 const double* lambda_e, double* gamma, double* force, double* grad_mass, void* ws,
                 size_t ws_bytes, void* stream);
 
+/* Workspace bytes for sp_hyp_smear on geometry g (24 FP64 link fields of V links). */
+size_t sp_hyp_workspace_bytes(const sp_geom* g);
+
+/* HYP smearing of SU(3) links, the smoothing applied to the links before the solve (the paper's quarks
+ * are HYP-smeared, Sec. 3; the paper does not define it, the definition is the hypercubic blocking of
+ * Hasenfratz and Knechtli). Three levels, each a weighted sum of a link and staples restricted to the
+ * hypercubes containing it, projected to SU(3):
+ *   lv1(mu, eta) = P[(1 - a3) U_mu + a3/2 S(U_eta; U_mu)]                              eta != mu
+ *   lv2(mu, nu)  = P[(1 - a2) U_mu + a2/4 sum_{rho not mu, nu} S(lv1(rho, s); lv1(mu, s))]
+ *                  s = the direction outside {mu, nu, rho}
+ *   V_mu         = P[(1 - a1) U_mu + a1/6 sum_{nu != mu} S(lv2(nu, mu); lv2(mu, nu))]
+ * with S(A; B)(x) = A_eta(x) B(x+eta) A_eta(x+mu)^dag + A_eta(x-eta)^dag B(x-eta) A_eta(x-eta+mu) for the
+ * staple direction eta of the sum, and P(W) = the SU(3) matrix maximising Re tr(X^dag W) (polar start
+ * with the determinant phase divided out, then SU(2)-subgroup sweeps to convergence).
+ * links_nat, out_nat: device, complex128 [4][V][3][3] in the natural layout (lex = x + X(y + Y(z + Z t)));
+ * they must not overlap. alpha: host, 3 doubles (a1, a2, a3), each in [0, 1]; (0.75, 0.6, 0.3) is the
+ * standard choice. All directions are periodic (bc_t is ignored: it is a fermion boundary condition).
+ * ws: device workspace of at least sp_hyp_workspace_bytes(g) bytes. Asynchronous on stream. */
+int sp_hyp_smear(const sp_geom* g, const double* links_nat, const double* alpha, double* out_nat, void* ws,
+                 size_t ws_bytes, void* stream);
+
 /* Workspace bytes for sp_full_solve. */
 size_t sp_full_workspace_bytes(const sp_geom* g, const sp_gauge* U, const sp_cg_params* params);
 

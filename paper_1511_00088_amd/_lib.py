@@ -75,6 +75,8 @@ SIGNATURES = {
     "sp_cg_force": (I, [PG, PU, D, P, P, P, P, P, P, SZ, P]),
     "sp_full_workspace_bytes": (SZ, [PG, PU, PP]),
     "sp_full_solve": (I, [PG, PU, D, P, P, PP, PS, P, SZ, P]),
+    "sp_hyp_workspace_bytes": (SZ, [PG]),
+    "sp_hyp_smear": (I, [PG, P, ctypes.POINTER(D), P, P, SZ, P]),
     "sp_tune_dslash": (I, [PG, PU, I, P, P, P, ctypes.POINTER(D)]),
     "sp_tune_save": (I, [ctypes.c_char_p]),
     "sp_tune_load": (I, [ctypes.c_char_p]),

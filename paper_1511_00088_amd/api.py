@@ -248,6 +248,27 @@ def cg_force(gauge: Gauge, mass: float, x: torch.Tensor, lam: torch.Tensor, want
     return gamma, force, dmass
 
 
+HYP_ALPHA = (0.75, 0.6, 0.3)
+
+
+def hyp_smear(lat: Lattice, links: torch.Tensor, alpha=HYP_ALPHA, out: torch.Tensor | None = None,
+              workspace: Workspace | None = None) -> torch.Tensor:
+    """HYP-smeared links (sp_hyp_smear): links complex128 [4][V][3][3] on the GPU -> a new tensor of the same
+    shape (or `out`). alpha = (a1, a2, a3), the weights of levels 3, 2 and 1."""
+    _check_c128(links, (4, lat.V, 3, 3), "links")
+    if out is None:
+        out = torch.empty_like(links)
+    else:
+        _check_c128(out, (4, lat.V, 3, 3), "out")
+    lib = L.load()
+    nbytes = int(lib.sp_hyp_workspace_bytes(ctypes.byref(lat.geom)))
+    ws = (workspace or _default_ws).get(nbytes, links.device)
+    a = (ctypes.c_double * 3)(*[float(x) for x in alpha])
+    L.check(lib.sp_hyp_smear(ctypes.byref(lat.geom), _ptr(links), a, _ptr(out), _ptr(ws), ctypes.c_size_t(nbytes),
+                             _stream()), "sp_hyp_smear")
+    return out
+
+
 def tune_dslash(gauge: Gauge, prec) -> float:
     """Pick the fastest launch shape of the half operator for this lattice and precision (ms per call)."""
     lat = gauge.lat

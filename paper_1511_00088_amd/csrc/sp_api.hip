@@ -1004,4 +1004,30 @@ int sp_full_solve(const sp_geom* g, const sp_gauge* U, double mass, const double
     return st;
 }
 
+size_t sp_hyp_workspace_bytes(const sp_geom* g) {
+    Geom G;
+    if (check_geom(g, &G)) return 0;
+    return hyp_workspace_bytes(G);
+}
+
+int sp_hyp_smear(const sp_geom* g, const double* links_nat, const double* alpha, double* out_nat, void* ws,
+                 size_t ws_bytes, void* stream) {
+    Geom G;
+    int rc = check_geom(g, &G);
+    if (rc) return rc;
+    if (!links_nat || !alpha || !out_nat) return fail(SP_ERR_INVALID_ARG, "null pointer");
+    for (int k = 0; k < 3; ++k)
+        if (!(alpha[k] >= 0.0 && alpha[k] <= 1.0)) return fail(SP_ERR_INVALID_ARG, "alpha[%d] not in [0, 1]", k);
+    const size_t field = 4ull * 2 * G.Vh * 18 * sizeof(double);
+    const char *a0 = (const char*)links_nat, *b0 = (const char*)out_nat;
+    if (a0 < b0 + field && b0 < a0 + field) return fail(SP_ERR_INVALID_ARG, "links and output overlap");
+    const size_t need = hyp_workspace_bytes(G);
+    if (!ws || ws_bytes < need) return fail(SP_ERR_WORKSPACE, "workspace %zu bytes < required %zu", ws_bytes, need);
+    if (((uintptr_t)ws) & 15) return fail(SP_ERR_INVALID_ARG, "workspace not 16-byte aligned");
+    if (((uintptr_t)links_nat) & 15 || ((uintptr_t)out_nat) & 15)
+        return fail(SP_ERR_INVALID_ARG, "links or output not 16-byte aligned");
+    HIP_TRY(launch_hyp(G, links_nat, alpha, out_nat, ws, (hipStream_t)stream));
+    return SP_OK;
+}
+
 }  // extern "C"

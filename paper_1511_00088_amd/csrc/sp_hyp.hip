@@ -1,0 +1,339 @@
+// HYP smearing of the gauge links (the smoothing the solver's links receive before the solve: the paper's
+// quarks are HYP-smeared, Sec. 3). Three levels of staple sums restricted to the hypercubes that contain
+// the link (the hypercubic blocking of Hasenfratz and Knechtli), each sum projected back to SU(3):
+//
+//   level 1  lv1(mu, eta):  (1 - a3) U_mu + a3/2 * staples of U_eta around U_mu        (12 fields)
+//   level 2  lv2(mu, nu):   (1 - a2) U_mu + a2/4 * sum_{rho not mu, nu} staples of lv1(rho, s) around
+//                           lv1(mu, s), s the direction outside {mu, nu, rho}              (12 fields)
+//   level 3  V_mu:          (1 - a1) U_mu + a1/6 * sum_{nu != mu} staples of lv2(nu, mu) around lv2(mu, nu)
+//
+// with staples of side S around top T in direction eta at x:
+//   S(x) T(x+eta) S(x+mu)^dag + S(x-eta)^dag T(x-eta) S(x-eta+mu).
+//
+// Proj_SU(3)(W) maximises Re tr(X^dag W) over SU(3). Start: the unitary polar factor of W by scaled Newton
+// iteration X <- (z X + X^-dag / z) / 2, z = |det X|^(-1/3), with the cube root of its determinant's phase
+// (principal branch) divided out; then sweeps over the three SU(2) subgroups (Cabibbo-Marinari), each
+// taking the subgroup element that maximises the objective, until a sweep moves no element by more than
+// 1e-15.
+//
+// One thread per (site, field); blockIdx.y selects the field, so a wavefront covers 64 consecutive sites
+// of one field. Every level is FP64. Input and output links use the natural layout [4][V][3][3] complex128
+// (a link is 9 consecutive double2); the intermediate fields live in the caller's workspace as planes
+// [9][V] double2 per field. All directions are periodic.
+#include "sp_launch.h"
+
+namespace sp {
+namespace {
+
+using C = Cx<double>;
+using M3 = Su3<double>;
+
+struct HypGeom {
+    int L[4];       // extents X, Y, Z, T
+    int stride[4];  // 1, X, XY, XYZ
+    int V;
+};
+
+__device__ __forceinline__ int hop(const HypGeom& g, int s, int mu, int d) {
+    const int c = (s / g.stride[mu]) % g.L[mu];
+    const int c1 = c + d;
+    int s1 = s + d * g.stride[mu];
+    if (c1 == g.L[mu]) s1 -= g.L[mu] * g.stride[mu];
+    if (c1 < 0) s1 += g.L[mu] * g.stride[mu];
+    return s1;
+}
+
+// A link field: element (site s, entry j) at p[s * ss + j * ps] (double2 units).
+struct LinkField {
+    const double2* p;
+    long ss, ps;
+};
+
+__device__ __forceinline__ M3 ld(const LinkField& f, int s) {
+    M3 m;
+#pragma unroll
+    for (int j = 0; j < 9; ++j) {
+        const double2 v = f.p[(long)s * f.ss + (long)j * f.ps];
+        m.e[j / 3][j % 3] = {v.x, v.y};
+    }
+    return m;
+}
+
+__device__ __forceinline__ void st(double2* p, long ss, long ps, int s, const M3& m) {
+#pragma unroll
+    for (int j = 0; j < 9; ++j) p[(long)s * ss + (long)j * ps] = make_double2(m.e[j / 3][j % 3].re, m.e[j / 3][j % 3].im);
+}
+
+__device__ __forceinline__ C cmul(C a, C b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+// a * conj(b)
+__device__ __forceinline__ C cmulc(C a, C b) { return {a.re * b.re + a.im * b.im, a.im * b.re - a.re * b.im}; }
+__device__ __forceinline__ C cadd(C a, C b) { return {a.re + b.re, a.im + b.im}; }
+__device__ __forceinline__ C csub(C a, C b) { return {a.re - b.re, a.im - b.im}; }
+
+// a b
+__device__ __forceinline__ M3 mul(const M3& a, const M3& b) {
+    M3 r;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            C s = cmul(a.e[i][0], b.e[0][j]);
+            s = cadd(s, cmul(a.e[i][1], b.e[1][j]));
+            r.e[i][j] = cadd(s, cmul(a.e[i][2], b.e[2][j]));
+        }
+    return r;
+}
+
+// a b^dag
+__device__ __forceinline__ M3 mul_nd(const M3& a, const M3& b) {
+    M3 r;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            C s = cmulc(a.e[i][0], b.e[j][0]);
+            s = cadd(s, cmulc(a.e[i][1], b.e[j][1]));
+            r.e[i][j] = cadd(s, cmulc(a.e[i][2], b.e[j][2]));
+        }
+    return r;
+}
+
+// a^dag b
+__device__ __forceinline__ M3 mul_dn(const M3& a, const M3& b) {
+    M3 r;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            C s = cmulc(b.e[0][j], a.e[0][i]);
+            s = cadd(s, cmulc(b.e[1][j], a.e[1][i]));
+            r.e[i][j] = cadd(s, cmulc(b.e[2][j], a.e[2][i]));
+        }
+    return r;
+}
+
+__device__ __forceinline__ void axpy(M3& w, double c, const M3& a) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            w.e[i][j].re += c * a.e[i][j].re;
+            w.e[i][j].im += c * a.e[i][j].im;
+        }
+}
+
+// w += c * [S(x) T(x+eta) S(x+mu)^dag + S(x-eta)^dag T(x-eta) S(x-eta+mu)]
+__device__ __forceinline__ void add_staples(M3& w, double c, const HypGeom& g, const LinkField& S, const LinkField& T,
+                                            int s, int mu, int eta) {
+    const int s_pe = hop(g, s, eta, +1), s_pm = hop(g, s, mu, +1), s_me = hop(g, s, eta, -1);
+    const int s_me_pm = hop(g, s_me, mu, +1);
+    axpy(w, c, mul_nd(mul(ld(S, s), ld(T, s_pe)), ld(S, s_pm)));
+    axpy(w, c, mul(mul_dn(ld(S, s_me), ld(T, s_me)), ld(S, s_me_pm)));
+}
+
+// rows of the cofactor matrix are cross products of the other two rows
+__device__ __forceinline__ void cross(const C* a, const C* b, C* out) {
+    out[0] = csub(cmul(a[1], b[2]), cmul(a[2], b[1]));
+    out[1] = csub(cmul(a[2], b[0]), cmul(a[0], b[2]));
+    out[2] = csub(cmul(a[0], b[1]), cmul(a[1], b[0]));
+}
+
+__device__ __forceinline__ C det3(const M3& x) {
+    C c[3];
+    cross(x.e[1], x.e[2], c);
+    return cadd(cadd(cmul(x.e[0][0], c[0]), cmul(x.e[0][1], c[1])), cmul(x.e[0][2], c[2]));
+}
+
+// The unitary polar factor of w by Newton's iteration with determinant scaling. X^-dag = conj(cof(X)) /
+// conj(det X), where the rows of cof(X) are r1 x r2, r2 x r0, r0 x r1.
+__device__ __forceinline__ M3 polar_factor(const M3& w) {
+    M3 x = w;
+    int extra = -1;
+    for (int it = 0; it < 40; ++it) {
+        M3 cof;
+        cross(x.e[1], x.e[2], cof.e[0]);
+        cross(x.e[2], x.e[0], cof.e[1]);
+        cross(x.e[0], x.e[1], cof.e[2]);
+        const C d = cadd(cadd(cmul(x.e[0][0], cof.e[0][0]), cmul(x.e[0][1], cof.e[0][1])),
+                         cmul(x.e[0][2], cof.e[0][2]));
+        const double ad2 = d.re * d.re + d.im * d.im;
+        const double z = 1.0 / cbrt(sqrt(ad2));
+        // X^-dag_ij = conj(cof_ij / d) = conj(cof_ij) * d / |d|^2
+        double diff = 0.0;
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                const C q = cmulc(d, cof.e[i][j]);  // d * conj(cof_ij)
+                const double nre = 0.5 * (z * x.e[i][j].re + q.re / (ad2 * z));
+                const double nim = 0.5 * (z * x.e[i][j].im + q.im / (ad2 * z));
+                diff = fmax(diff, fmax(fabs(nre - x.e[i][j].re), fabs(nim - x.e[i][j].im)));
+                x.e[i][j] = {nre, nim};
+            }
+        // quadratic convergence: once the step is small, two more steps reach rounding level
+        if (extra < 0 && diff < 1e-6) extra = 2;
+        if (extra >= 0 && extra-- == 0) break;
+    }
+    return x;
+}
+
+__device__ __forceinline__ void su2_step(M3& x, const M3& w, int i, int j) {
+    // entries (i,i), (i,j), (j,i), (j,j) of M = W X^dag
+    auto m = [&](int a, int b) {
+        C s = cmulc(w.e[a][0], x.e[b][0]);
+        s = cadd(s, cmulc(w.e[a][1], x.e[b][1]));
+        return cadd(s, cmulc(w.e[a][2], x.e[b][2]));
+    };
+    const C mii = m(i, i), mij = m(i, j), mji = m(j, i), mjj = m(j, j);
+    // Re tr(h^dag A) over h = b0 + i b.sigma in SU(2) is 2 (b0 Re A0 + b . Re A), A = A0 + i A.sigma
+    const double a0 = 0.5 * (mii.re + mjj.re);
+    const double a1 = 0.5 * (mij.im + mji.im);
+    const double a2 = 0.5 * (mij.re - mji.re);
+    const double a3 = 0.5 * (mii.im - mjj.im);
+    const double rn = 1.0 / sqrt(a0 * a0 + a1 * a1 + a2 * a2 + a3 * a3);
+    const double b0 = a0 * rn, b1 = a1 * rn, b2 = a2 * rn, b3 = a3 * rn;
+    const C h00 = {b0, b3}, h01 = {b2, b1}, h10 = {-b2, b1}, h11 = {b0, -b3};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const C xi = x.e[i][k], xj = x.e[j][k];
+        x.e[i][k] = cadd(cmul(h00, xi), cmul(h01, xj));
+        x.e[j][k] = cadd(cmul(h10, xi), cmul(h11, xj));
+    }
+}
+
+__device__ __forceinline__ M3 proj_su3(const M3& w) {
+    M3 x = polar_factor(w);
+    const C d = det3(x);
+    const double th = -atan2(d.im, d.re) / 3.0;
+    const C ph = {cos(th), sin(th)};
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) x.e[i][j] = cmul(x.e[i][j], ph);
+    for (int sweep = 0; sweep < 200; ++sweep) {
+        const M3 x0 = x;
+        su2_step(x, w, 0, 1);
+        su2_step(x, w, 0, 2);
+        su2_step(x, w, 1, 2);
+        double diff = 0.0;
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                const double dr = x.e[i][j].re - x0.e[i][j].re, di = x.e[i][j].im - x0.e[i][j].im;
+                diff = fmax(diff, sqrt(dr * dr + di * di));
+            }
+        if (diff <= 1e-15) break;
+    }
+    return x;
+}
+
+__device__ __forceinline__ int other(int a, int k) { return k < a ? k : k + 1; }  // k-th direction != a
+__device__ __forceinline__ int fidx(int a, int b) { return a * 3 + (b < a ? b : b - 1); }  // field (a, b != a)
+
+struct HypArgs {
+    HypGeom g;
+    const double2* U;  // natural [4][V][9] double2
+    double2* lv1;      // [12][9][V]
+    double2* lv2;      // [12][9][V]
+    double2* out;      // natural [4][V][9]
+    double a1, a2, a3;
+};
+
+__device__ __forceinline__ LinkField nat(const HypArgs& a, const double2* base, int mu) {
+    return {base + (long)mu * a.g.V * 9, 9, 1};
+}
+__device__ __forceinline__ LinkField plane(const HypArgs& a, const double2* base, int f) {
+    return {base + (long)f * a.g.V * 9, 1, a.g.V};
+}
+
+__global__ __launch_bounds__(256) void k_hyp_level1(HypArgs a) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= a.g.V) return;
+    const int f = blockIdx.y, mu = f / 3, eta = other(mu, f % 3);
+    const LinkField Um = nat(a, a.U, mu);
+    M3 w = ld(Um, s);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            w.e[i][j].re *= 1.0 - a.a3;
+            w.e[i][j].im *= 1.0 - a.a3;
+        }
+    add_staples(w, 0.5 * a.a3, a.g, nat(a, a.U, eta), Um, s, mu, eta);
+    st(a.lv1 + (long)f * a.g.V * 9, 1, a.g.V, s, proj_su3(w));
+}
+
+__global__ __launch_bounds__(256) void k_hyp_level2(HypArgs a) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= a.g.V) return;
+    const int f = blockIdx.y, mu = f / 3, nu = other(mu, f % 3);
+    M3 w = ld(nat(a, a.U, mu), s);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            w.e[i][j].re *= 1.0 - a.a2;
+            w.e[i][j].im *= 1.0 - a.a2;
+        }
+    for (int rho = 0; rho < 4; ++rho) {
+        if (rho == mu || rho == nu) continue;
+        const int sg = 6 - mu - nu - rho;
+        add_staples(w, 0.25 * a.a2, a.g, plane(a, a.lv1, fidx(rho, sg)), plane(a, a.lv1, fidx(mu, sg)), s, mu, rho);
+    }
+    st(a.lv2 + (long)f * a.g.V * 9, 1, a.g.V, s, proj_su3(w));
+}
+
+__global__ __launch_bounds__(256) void k_hyp_level3(HypArgs a) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= a.g.V) return;
+    const int mu = blockIdx.y;
+    M3 w = ld(nat(a, a.U, mu), s);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            w.e[i][j].re *= 1.0 - a.a1;
+            w.e[i][j].im *= 1.0 - a.a1;
+        }
+    for (int nu = 0; nu < 4; ++nu) {
+        if (nu == mu) continue;
+        add_staples(w, a.a1 / 6.0, a.g, plane(a, a.lv2, fidx(nu, mu)), plane(a, a.lv2, fidx(mu, nu)), s, mu, nu);
+    }
+    st(a.out + (long)mu * a.g.V * 9, 9, 1, s, proj_su3(w));
+}
+
+}  // namespace
+
+size_t hyp_workspace_bytes(const Geom& g) { return 24ull * 2 * (size_t)g.Vh * 9 * sizeof(double2); }
+
+hipError_t launch_hyp(const Geom& g, const double* links, const double alpha[3], double* out, void* ws,
+                      hipStream_t s) {
+    HypArgs a;
+    a.g.L[0] = g.X;
+    a.g.L[1] = g.Y;
+    a.g.L[2] = g.Z;
+    a.g.L[3] = g.T;
+    a.g.stride[0] = 1;
+    a.g.stride[1] = g.X;
+    a.g.stride[2] = g.X * g.Y;
+    a.g.stride[3] = g.X * g.Y * g.Z;
+    a.g.V = 2 * g.Vh;
+    a.U = (const double2*)links;
+    a.lv1 = (double2*)ws;
+    a.lv2 = (double2*)ws + 12L * a.g.V * 9;
+    a.out = (double2*)out;
+    a.a1 = alpha[0];
+    a.a2 = alpha[1];
+    a.a3 = alpha[2];
+    const unsigned nb = (unsigned)blocks_for(a.g.V, 256);
+    hipLaunchKernelGGL(k_hyp_level1, dim3(nb, 12), dim3(256), 0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e) return e;
+    hipLaunchKernelGGL(k_hyp_level2, dim3(nb, 12), dim3(256), 0, s, a);
+    if ((e = hipGetLastError())) return e;
+    hipLaunchKernelGGL(k_hyp_level3, dim3(nb, 4), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace sp

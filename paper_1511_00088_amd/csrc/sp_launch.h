@@ -61,4 +61,9 @@ hipError_t launch_full_source(const Geom& g, double m, const void* se, const voi
 hipError_t launch_full_merge(const Geom& g, double m, const double* psie, const void* so, const void* to,
                              double* psi, hipStream_t s);
 
+// HYP smearing (sp_hyp.hip): three launches, intermediate levels in ws (hyp_workspace_bytes).
+size_t hyp_workspace_bytes(const Geom& g);
+hipError_t launch_hyp(const Geom& g, const double* links, const double alpha[3], double* out, void* ws,
+                      hipStream_t s);
+
 }  // namespace sp

@@ -69,6 +69,27 @@ def test_workspace_query_and_validation():
     assert rc == _lib.SP_ERR_INVALID_ARG
 
 
+def test_hyp_workspace_and_validation():
+    # every check below fails before any device memory is touched, so fake pointers are safe
+    lib = _lib.load()
+    lat = sp.Lattice((20, 20, 20, 64))
+    n = lib.sp_hyp_workspace_bytes(ctypes.byref(lat.geom))
+    assert n == 24 * 512000 * 144
+    odd = _lib.sp_geom((ctypes.c_int32 * 4)(4, 4, 3, 4), 0)
+    assert lib.sp_hyp_workspace_bytes(ctypes.byref(odd)) == 0
+    a = (ctypes.c_double * 3)(0.75, 0.6, 0.3)
+    bad = (ctypes.c_double * 3)(0.75, -0.1, 0.3)
+    L, O = 1 << 20, 1 << 40  # links and output far apart
+    field = 4 * 512000 * 144
+    g = ctypes.byref(lat.geom)
+    assert lib.sp_hyp_smear(g, L, bad, O, 1 << 44, n, None) == _lib.SP_ERR_INVALID_ARG
+    assert lib.sp_hyp_smear(g, None, a, O, 1 << 44, n, None) == _lib.SP_ERR_INVALID_ARG
+    assert lib.sp_hyp_smear(g, L, a, L + field // 2, 1 << 44, n, None) == _lib.SP_ERR_INVALID_ARG  # overlap
+    assert lib.sp_hyp_smear(g, L, a, O, 1 << 44, n - 16, None) == _lib.SP_ERR_WORKSPACE
+    assert lib.sp_hyp_smear(g, L, a, O, None, n, None) == _lib.SP_ERR_WORKSPACE
+    assert lib.sp_hyp_smear(ctypes.byref(odd), L, a, O, 1 << 44, n, None) == _lib.SP_ERR_ODD_EXTENT
+
+
 def test_tune_cache_roundtrip(tmp_path):
     lib = _lib.load()
     p = tmp_path / "tune.json"

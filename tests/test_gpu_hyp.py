@@ -1,0 +1,110 @@
+"""GPU HYP smearing (sp_hyp_smear) against the FP64 oracle (oracle/hyp.py).
+
+Small lattices are compared link by link with the oracle's full result; the 20^3x64 workload field at
+sampled links against the committed oracle values (tests/golden/hyp_cfg1_samples.txt), plus properties
+that hold at any size (every output link in SU(3), determinism). Both sides maximise Re tr(X^dag W) from
+the same start by the same published iteration; they differ in how the start is computed (SVD on the
+oracle side, Newton's polar iteration on the GPU) and in rounding, so agreement is to ~1e-13.
+"""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import lattice_inputs as li
+import paper_1511_00088_amd as sp
+from gpu_common import DEV, announce, to_dev, to_host
+from oracle import hyp
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "hyp_cfg1_samples.txt")
+
+
+def _gpu_hyp(dims, U, alpha=hyp.HYP_ALPHA):
+    lat = sp.Lattice(dims)
+    out = sp.hyp_smear(lat, to_dev(U), alpha)
+    torch.cuda.synchronize()
+    return to_host(out)
+
+
+@pytest.mark.parametrize("dims,kind,alpha", [
+    ((4, 4, 4, 4), "near", hyp.HYP_ALPHA),
+    ((4, 6, 2, 8), "near", hyp.HYP_ALPHA),
+    ((6, 4, 4, 6), "near", (0.5, 0.3, 0.9)),
+    ((4, 4, 4, 4), "haar", hyp.HYP_ALPHA),
+    ((8, 8, 8, 8), "near", hyp.HYP_ALPHA),
+])
+def test_hyp_matches_oracle(dims, kind, alpha):
+    announce(f"hyp dims={dims} {kind} alpha={alpha}")
+    U = li.near_identity_links(dims, 0.5, 451) if kind == "near" else li.haar_links(dims, 452)
+    V = _gpu_hyp(dims, U, alpha)
+    ref = hyp.hyp_smear(dims, U, alpha)
+    assert np.max(np.abs(V - ref)) <= 1e-12
+
+
+def test_zero_weights_give_the_links_back():
+    dims = (4, 4, 4, 4)
+    announce("hyp zero weights")
+    U = li.haar_links(dims, 453)
+    assert np.max(np.abs(_gpu_hyp(dims, U, (0.0, 0.0, 0.0)) - U)) <= 1e-13
+
+
+def _golden():
+    rows = np.loadtxt(GOLDEN, comments="#")
+    mu = rows[:, 0].astype(int)
+    s = rows[:, 1].astype(int)
+    m = (rows[:, 2::2] + 1j * rows[:, 3::2]).reshape(-1, 3, 3)
+    return mu, s, m
+
+
+def test_workload_field_sampled_vs_oracle_and_su3_everywhere():
+    c = li.cfg1()
+    dims = c["dims"]
+    announce(f"hyp {dims} sampled")
+    lat = sp.Lattice(dims)
+    U = to_dev(c["links"])
+    out = sp.hyp_smear(lat, U)
+    out2 = sp.hyp_smear(lat, U)
+    torch.cuda.synchronize()
+    assert torch.equal(out, out2)  # deterministic
+    mu, s, ref = _golden()
+    got = to_host(out[torch.as_tensor(mu, device=DEV), torch.as_tensor(s, device=DEV)])
+    assert np.max(np.abs(got - ref)) <= 1e-12
+    # every output link is in SU(3)
+    eye = torch.eye(3, dtype=torch.complex128, device=DEV)
+    for m in range(4):
+        Vm = out[m]
+        un = torch.max(torch.abs(Vm @ Vm.conj().transpose(-1, -2) - eye)).item()
+        dt = torch.max(torch.abs(torch.linalg.det(Vm) - 1.0)).item()
+        assert un <= 1e-13 and dt <= 1e-13, (m, un, dt)
+
+
+def test_smeared_links_feed_the_solver():
+    # the product of this step is a link field for the solve: smear, pack, solve, compare with the oracle
+    import oracle
+
+    dims = (4, 4, 4, 4)
+    announce("hyp then solve 4^4")
+    U = li.near_identity_links(dims, 0.5, 454)
+    b = li.gaussian_even_source(dims, 455)
+    m = 0.1
+    lat = sp.Lattice(dims)
+    Vs = sp.hyp_smear(lat, to_dev(U))
+    G = sp.Gauge(lat, Vs, lo_prec="f32", recon=12)
+    x, st = sp.cg_solve(G, m, to_dev(b), tol=1e-10, inner="f32")
+    assert st.converged
+    xr, status, _, _ = oracle.cg_solve(dims, hyp.hyp_smear(dims, U), m, b, tol=1e-13)
+    assert status == 0
+    assert np.linalg.norm(to_host(x) - xr) / np.linalg.norm(xr) <= 1e-8
+
+
+def test_errors():
+    dims = (4, 4, 4, 4)
+    lat = sp.Lattice(dims)
+    U = to_dev(li.haar_links(dims, 456))
+    with pytest.raises(sp.StagError):
+        sp.hyp_smear(lat, U, (0.75, 1.5, 0.3))
+    with pytest.raises(sp.StagError):
+        sp.hyp_smear(lat, U, out=U)
