@@ -278,7 +278,7 @@ def main():
                     help="skip the 16-bit storage solves, the batched workload and the gradient timing")
     ap.add_argument("--tune-file", default=os.path.join(ROOT, "paper_1511_00088_amd", "tune_mi355x.json"),
                     help="tuned launch table to load (tunes in-process when the file is missing)")
-    ap.add_argument("--mode", default="bench", choices=["bench", "traffic"],
+    ap.add_argument("--mode", default="bench", choices=["bench", "traffic", "hyp"],
                     help="traffic: only a 1 GiB device copy (counter calibration) and the half-Dslash "
                          "launches, for hardware-counter runs")
     args = ap.parse_args()
@@ -333,6 +333,11 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"mode": "traffic", "copy_bytes": n, "dslash_launches": 20,
                           "dslash_algorithmic_bytes": dslash_bytes_per_site(args.inner, args.recon) * lat.Vh}))
+        return
+
+    if args.mode == "hyp":
+        # the HYP smearing of the workload field alone (for a kernel trace of its three launches)
+        print(json.dumps({"mode": "hyp", **bench_hyp(sp, torch, lat, G64_links(), stream, log)}))
         return
 
     def solve_mixed():

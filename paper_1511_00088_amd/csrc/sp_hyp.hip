@@ -158,6 +158,7 @@ __device__ __forceinline__ M3 polar_factor(const M3& w) {
                          cmul(x.e[0][2], cof.e[0][2]));
         const double ad2 = d.re * d.re + d.im * d.im;
         const double z = 1.0 / cbrt(sqrt(ad2));
+        const double hz = 0.5 * z, hr = 0.5 / (ad2 * z);
         // X^-dag_ij = conj(cof_ij / d) = conj(cof_ij) * d / |d|^2
         double diff = 0.0;
 #pragma unroll
@@ -165,8 +166,8 @@ __device__ __forceinline__ M3 polar_factor(const M3& w) {
 #pragma unroll
             for (int j = 0; j < 3; ++j) {
                 const C q = cmulc(d, cof.e[i][j]);  // d * conj(cof_ij)
-                const double nre = 0.5 * (z * x.e[i][j].re + q.re / (ad2 * z));
-                const double nim = 0.5 * (z * x.e[i][j].im + q.im / (ad2 * z));
+                const double nre = hz * x.e[i][j].re + hr * q.re;
+                const double nim = hz * x.e[i][j].im + hr * q.im;
                 diff = fmax(diff, fmax(fabs(nre - x.e[i][j].re), fabs(nim - x.e[i][j].im)));
                 x.e[i][j] = {nre, nim};
             }
@@ -215,15 +216,15 @@ __device__ __forceinline__ M3 proj_su3(const M3& w) {
         su2_step(x, w, 0, 1);
         su2_step(x, w, 0, 2);
         su2_step(x, w, 1, 2);
-        double diff = 0.0;
+        double diff2 = 0.0;  // largest |change|^2 of an element
 #pragma unroll
         for (int i = 0; i < 3; ++i)
 #pragma unroll
             for (int j = 0; j < 3; ++j) {
                 const double dr = x.e[i][j].re - x0.e[i][j].re, di = x.e[i][j].im - x0.e[i][j].im;
-                diff = fmax(diff, sqrt(dr * dr + di * di));
+                diff2 = fmax(diff2, dr * dr + di * di);
             }
-        if (diff <= 1e-15) break;
+        if (diff2 <= 1e-30) break;
     }
     return x;
 }
