@@ -183,8 +183,9 @@ __global__ __launch_bounds__(256) void k_dslash(D d, int p, int in_slot, int out
     if (live) {
         const Site s = site_of(g, p, cb);
 // one direction at a time for several systems (their gathers would not fit in registers otherwise); two at
-// a time in FP64, where all four put 384 values in flight and leave one wave per SIMD
-#pragma unroll(N == 1 ? (VP == F64 ? 2 : 4) : 1)
+// a time in FP64, where all four put 384 values in flight and leave one wave per SIMD, and for FP32
+// recon-12, whose row rebuild makes four at a time cost 125-136 VGPRs (measured 3-4% slower)
+#pragma unroll(N == 1 ? ((VP == F64 || (LP == F32 && RECON == 12)) ? 2 : 4) : 1)
         for (int mu = 0; mu < 4; ++mu) {
             R e = (R)eta_sign(s, mu);
             R sf = e, sb = -e;
