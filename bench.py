@@ -225,6 +225,50 @@ def bench_hyp(sp, torch, lat, links, stream, log):
                     "bound by FP64 arithmetic, not bytes"}
 
 
+# NPR contraction: flop per (field set, hypercube): 256 terms, each two bilinears chib^T U chi (U chi: 9
+# complex multiply-adds = 66 flop, the dot with chib: 22 flop), their product (6) and the signed sum (4)
+NPR_FLOP_PER_Z = 256 * (2 * (66 + 22) + 10)
+NPR_SETS = 4  # field sets per contraction launch
+
+
+def bench_npr(sp, torch, lat, links, stream, log):
+    """The NPR one-colour-trace contraction on the workload lattice: path links once, then a contraction of
+    NPR_SETS Gaussian field sets (labels gamma_5 x xi_5 for both bilinears), HIP events."""
+    gen = torch.Generator(device=links.device)
+    gen.manual_seed(61)
+    f = [torch.randn(NPR_SETS, lat.V, 3, dtype=torch.complex128, device=links.device, generator=gen)
+         for _ in range(4)]
+    labels = (15, 15, 15, 15)
+    uad = sp.npr_path_links(lat, links)
+    sp.npr_contract(lat, uad, *f, labels)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    n = 10
+    e0.record(stream)
+    for _ in range(n):
+        sp.npr_path_links(lat, links)
+    e1.record(stream)
+    e1.synchronize()
+    t_p = e0.elapsed_time(e1) / 1e3 / n
+    e0.record(stream)
+    for _ in range(n):
+        sp.npr_contract(lat, uad, *f, labels)
+    e1.record(stream)
+    e1.synchronize()
+    t_c = e0.elapsed_time(e1) / 1e3 / n
+    nz = lat.V // 16
+    bytes_c = nz * (256 * 144 + NPR_SETS * (4 * 16 * 48 + 16))
+    res = {"dims": list(lat.dims), "sets": NPR_SETS, "labels": list(labels), "paths_ms": t_p * 1e3,
+           "contract_ms": t_c * 1e3, "contract_gflops": NPR_FLOP_PER_Z * NPR_SETS * nz / t_c / 1e9,
+           "contract_bytes": bytes_c, "contract_GBs": bytes_c / t_c / 1e9,
+           "contract_hbm_frac": bytes_c / t_c / 1e9 / HBM_PEAK_GBS,
+           "paths_bytes": lat.V * 4 * 144 + nz * 256 * 144,
+           "paths_GBs": (lat.V * 4 * 144 + nz * 256 * 144) / t_p / 1e9}
+    log(f"NPR: path links {t_p * 1e3:.3f} ms, contraction of {NPR_SETS} sets {t_c * 1e3:.3f} ms "
+        f"({res['contract_gflops']:.0f} GFLOP/s, {res['contract_GBs']:.0f} GB/s)")
+    return res
+
+
 def bench_gradient(sp, li, torch, dev, log):
     """16^3x32, m = 0.05: loss Re phi^dag A^-1 phi, forward solve + adjoint solve + force kernels."""
     c = li.cfg4()
@@ -278,7 +322,7 @@ def main():
                     help="skip the 16-bit storage solves, the batched workload and the gradient timing")
     ap.add_argument("--tune-file", default=os.path.join(ROOT, "paper_1511_00088_amd", "tune_mi355x.json"),
                     help="tuned launch table to load (tunes in-process when the file is missing)")
-    ap.add_argument("--mode", default="bench", choices=["bench", "traffic", "hyp"],
+    ap.add_argument("--mode", default="bench", choices=["bench", "traffic", "hyp", "npr"],
                     help="traffic: only a 1 GiB device copy (counter calibration) and the half-Dslash "
                          "launches, for hardware-counter runs")
     args = ap.parse_args()
@@ -333,6 +377,11 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"mode": "traffic", "copy_bytes": n, "dslash_launches": 20,
                           "dslash_algorithmic_bytes": dslash_bytes_per_site(args.inner, args.recon) * lat.Vh}))
+        return
+
+    if args.mode == "npr":
+        # the NPR contraction alone (for a kernel trace of its two launches)
+        print(json.dumps({"mode": "npr", **bench_npr(sp, torch, lat, G64_links(), stream, log)}))
         return
 
     if args.mode == "hyp":
@@ -469,6 +518,7 @@ def main():
                 del Gl
         extra["storage_16bit"] = low
         extra["hyp"] = bench_hyp(sp, torch, lat, G64_links(), stream, log)
+        extra["npr"] = bench_npr(sp, torch, lat, G64_links(), stream, log)
         extra["batched"] = bench_batched(sp, li, torch, dev, log)
         extra["gradient"] = bench_gradient(sp, li, torch, dev, log)
 

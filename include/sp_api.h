@@ -206,6 +206,29 @@ size_t sp_hyp_workspace_bytes(const sp_geom* g);
 int sp_hyp_smear(const sp_geom* g, const double* links_nat, const double* alpha, double* out_nat, void* ws,
                  size_t ws_bytes, void* stream);
 
+/* Bytes of the path-link array of sp_npr_path_links on geometry g: 256 complex128 3x3 matrices per
+ * hypercube (V/16 hypercubes). */
+size_t sp_npr_path_bytes(const sp_geom* g);
+
+/* Path links of the NPR four-fermion contraction (the paper's Eq. (1), Sec. 4, the U_{i;AD}(z) factors):
+ * for every hypercube z (corners z_A = 2z + A, A in {0,1}^4, A = A0 + 2A1 + 4A2 + 8A3; hypercubes in
+ * lexicographic order of the coarse lattice X/2 x Y/2 x Z/2 x T/2) and every corner pair (A, D), the average
+ * over the shortest paths from z_A to z_D of the ordered link products (a step +mu from x takes U_mu(x), a
+ * step -mu takes U_mu(x - mu)^dag; U_AA = 1). links_nat: device, complex128 [4][V][3][3]; uad: device,
+ * sp_npr_path_bytes(g) bytes, written as complex128 [V/16][16 A][16 D][3][3]. Asynchronous on stream. */
+int sp_npr_path_links(const sp_geom* g, const double* links_nat, void* uad, void* stream);
+
+/* The one-colour-trace four-fermion contraction (the paper's Eq. (1), Sec. 4), per hypercube z and field
+ * set i = 0..n-1:
+ *   O_i(z) = sum_{A,B,C,D} M1_{AB} M2_{CD} [chib1(z_A)^T U_AD(z) chi4(z_D)] [chib3(z_C)^T U_CB(z) chi2(z_B)]
+ * with chib^T U chi = sum_{c,c'} chib_c U_cc' chi_c' and the spin-taste matrices
+ * M_{AB} = (1/4) tr(gamma_A^dag gamma_S gamma_B gamma_F^dag), gamma_A = g1^A0 g2^A1 g3^A2 g4^A3 (Hermitian
+ * Euclidean Dirac matrices). labels: host, 4 ints (S1, F1, S2, F2), each a 4-bit spin or taste label in
+ * [0, 16). uad: from sp_npr_path_links. chib1, chi2, chib3, chi4: device, complex128 [n][V][3] (natural
+ * layout, no conjugation implied). out: device, complex128 [n][V/16]. Asynchronous on stream. */
+int sp_npr_contract(const sp_geom* g, const void* uad, int n, const double* chib1, const double* chi2,
+                    const double* chib3, const double* chi4, const int32_t* labels, double* out, void* stream);
+
 /* Workspace bytes for sp_full_solve. */
 size_t sp_full_workspace_bytes(const sp_geom* g, const sp_gauge* U, const sp_cg_params* params);
 

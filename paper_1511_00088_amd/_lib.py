@@ -77,6 +77,9 @@ SIGNATURES = {
     "sp_full_solve": (I, [PG, PU, D, P, P, PP, PS, P, SZ, P]),
     "sp_hyp_workspace_bytes": (SZ, [PG]),
     "sp_hyp_smear": (I, [PG, P, ctypes.POINTER(D), P, P, SZ, P]),
+    "sp_npr_path_bytes": (SZ, [PG]),
+    "sp_npr_path_links": (I, [PG, P, P, P]),
+    "sp_npr_contract": (I, [PG, P, I, P, P, P, P, ctypes.POINTER(ctypes.c_int32), P, P]),
     "sp_tune_dslash": (I, [PG, PU, I, P, P, P, ctypes.POINTER(D)]),
     "sp_tune_save": (I, [ctypes.c_char_p]),
     "sp_tune_load": (I, [ctypes.c_char_p]),

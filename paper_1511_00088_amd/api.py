@@ -269,6 +269,28 @@ def hyp_smear(lat: Lattice, links: torch.Tensor, alpha=HYP_ALPHA, out: torch.Ten
     return out
 
 
+def npr_path_links(lat: Lattice, links: torch.Tensor) -> torch.Tensor:
+    """U_AD(z) of the NPR contraction (sp_npr_path_links): complex128 [V/16][16][16][3][3]."""
+    _check_c128(links, (4, lat.V, 3, 3), "links")
+    out = torch.empty(lat.V // 16, 16, 16, 3, 3, dtype=torch.complex128, device=links.device)
+    L.check(L.load().sp_npr_path_links(ctypes.byref(lat.geom), _ptr(links), _ptr(out), _stream()), "sp_npr_path_links")
+    return out
+
+
+def npr_contract(lat: Lattice, uad: torch.Tensor, chib1, chi2, chib3, chi4, labels) -> torch.Tensor:
+    """O_i(z) of the one-colour-trace four-fermion contraction (sp_npr_contract): fields complex128 [n][V][3],
+    labels (S1, F1, S2, F2) -> complex128 [n][V/16]."""
+    _check_c128(uad, (lat.V // 16, 16, 16, 3, 3), "uad")
+    n = chib1.shape[0]
+    for name, f in (("chib1", chib1), ("chi2", chi2), ("chib3", chib3), ("chi4", chi4)):
+        _check_c128(f, (n, lat.V, 3), name)
+    out = torch.empty(n, lat.V // 16, dtype=torch.complex128, device=uad.device)
+    lab = (ctypes.c_int32 * 4)(*[int(x) for x in labels])
+    L.check(L.load().sp_npr_contract(ctypes.byref(lat.geom), _ptr(uad), int(n), _ptr(chib1), _ptr(chi2), _ptr(chib3),
+                                     _ptr(chi4), lab, _ptr(out), _stream()), "sp_npr_contract")
+    return out
+
+
 def tune_dslash(gauge: Gauge, prec) -> float:
     """Pick the fastest launch shape of the half operator for this lattice and precision (ms per call)."""
     lat = gauge.lat

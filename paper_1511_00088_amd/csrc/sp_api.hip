@@ -1030,4 +1030,39 @@ int sp_hyp_smear(const sp_geom* g, const double* links_nat, const double* alpha,
     return SP_OK;
 }
 
+size_t sp_npr_path_bytes(const sp_geom* g) {
+    Geom G;
+    if (check_geom(g, &G)) return 0;
+    return npr_path_bytes(G);
+}
+
+int sp_npr_path_links(const sp_geom* g, const double* links_nat, void* uad, void* stream) {
+    Geom G;
+    int rc = check_geom(g, &G);
+    if (rc) return rc;
+    if (!links_nat || !uad) return fail(SP_ERR_INVALID_ARG, "null pointer");
+    if (((uintptr_t)links_nat) & 15 || ((uintptr_t)uad) & 15) return fail(SP_ERR_INVALID_ARG, "pointers not 16-byte aligned");
+    HIP_TRY(launch_npr_paths(G, links_nat, uad, (hipStream_t)stream));
+    return SP_OK;
+}
+
+int sp_npr_contract(const sp_geom* g, const void* uad, int n, const double* chib1, const double* chi2,
+                    const double* chib3, const double* chi4, const int32_t* labels, double* out, void* stream) {
+    Geom G;
+    int rc = check_geom(g, &G);
+    if (rc) return rc;
+    if (!uad || !chib1 || !chi2 || !chib3 || !chi4 || !labels || !out) return fail(SP_ERR_INVALID_ARG, "null pointer");
+    if (n < 1) return fail(SP_ERR_INVALID_ARG, "n must be >= 1");
+    int lab[4];
+    for (int k = 0; k < 4; ++k) {
+        if (labels[k] < 0 || labels[k] > 15) return fail(SP_ERR_INVALID_ARG, "label %d not in [0, 16)", k);
+        lab[k] = labels[k];
+    }
+    const double* f[4] = {chib1, chi2, chib3, chi4};
+    for (int k = 0; k < 4; ++k)
+        if (((uintptr_t)f[k]) & 15) return fail(SP_ERR_INVALID_ARG, "field %d not 16-byte aligned", k);
+    HIP_TRY(launch_npr_contract(G, uad, n, f, lab, out, (hipStream_t)stream));
+    return SP_OK;
+}
+
 }  // extern "C"

@@ -66,4 +66,10 @@ size_t hyp_workspace_bytes(const Geom& g);
 hipError_t launch_hyp(const Geom& g, const double* links, const double alpha[3], double* out, void* ws,
                       hipStream_t s);
 
+// NPR contraction (sp_npr.hip): path links per hypercube, then the contraction of n field sets.
+size_t npr_path_bytes(const Geom& g);
+hipError_t launch_npr_paths(const Geom& g, const double* links, void* uad, hipStream_t s);
+hipError_t launch_npr_contract(const Geom& g, const void* uad, int n, const double* const f[4], const int labels[4],
+                               double* out, hipStream_t s);
+
 }  // namespace sp

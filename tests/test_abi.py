@@ -90,6 +90,20 @@ def test_hyp_workspace_and_validation():
     assert lib.sp_hyp_smear(ctypes.byref(odd), L, a, O, 1 << 44, n, None) == _lib.SP_ERR_ODD_EXTENT
 
 
+def test_npr_sizes_and_validation():
+    lib = _lib.load()
+    lat = sp.Lattice((20, 20, 20, 64))
+    assert lib.sp_npr_path_bytes(ctypes.byref(lat.geom)) == 32000 * 256 * 144
+    g = ctypes.byref(lat.geom)
+    ok = (ctypes.c_int32 * 4)(15, 15, 15, 15)
+    bad = (ctypes.c_int32 * 4)(15, 16, 15, 15)
+    F = 1 << 30  # never touched: every call below fails its checks first
+    assert lib.sp_npr_contract(g, F, 1, F, F, F, F, bad, F, None) == _lib.SP_ERR_INVALID_ARG
+    assert lib.sp_npr_contract(g, F, 0, F, F, F, F, ok, F, None) == _lib.SP_ERR_INVALID_ARG
+    assert lib.sp_npr_contract(g, None, 1, F, F, F, F, ok, F, None) == _lib.SP_ERR_INVALID_ARG
+    assert lib.sp_npr_path_links(g, None, F, None) == _lib.SP_ERR_INVALID_ARG
+
+
 def test_tune_cache_roundtrip(tmp_path):
     lib = _lib.load()
     p = tmp_path / "tune.json"
