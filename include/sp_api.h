@@ -240,9 +240,12 @@ int sp_full_solve(const sp_geom* g, const sp_gauge* U, double mass, const double
                   const sp_cg_params* params, sp_cg_stats* stats, void* ws, size_t ws_bytes, void* stream);
 
 /* Autotune the half-operator launch (block size, XCD-aware block order) for (g, prec, U->recon) by
- * timing it with HIP events on stream; in and out are scratch packed vectors of that precision. The
- * choice is kept for the process and used by sp_dslash and the solvers. best_ms (host, nullable)
- * receives the best time per launch. */
+ * timing it with HIP events on stream, for one right-hand side and for the 4-right-hand-side operator of
+ * batched solves (which has its own register use); in and out are scratch packed vectors of that
+ * precision. The 4-right-hand-side timing uses a temporary device buffer of 8 vectors plus descriptors,
+ * allocated and freed inside the call. The choices are kept for the process and used by sp_dslash and the
+ * solvers (sp_tune_save writes both; the batched one under the key suffix "/n4"). best_ms (host,
+ * nullable) receives the best one-right-hand-side time per launch. Synchronous with respect to stream. */
 int sp_tune_dslash(const sp_geom* g, const sp_gauge* U, int prec, void* in, void* out, void* stream,
                    double* best_ms);
 

@@ -119,6 +119,12 @@ LaunchCfg tuned_cfg(const Geom& g, int lp, int recon, int vp) {
     return it == g_tune.end() ? LaunchCfg{} : it->second;
 }
 
+// Launch shape of the NB-right-hand-side operator ("/n4" entry), else the single-system one.
+LaunchCfg tuned_cfg_batched(const Geom& g, int lp, int recon, int vp) {
+    auto it = g_tune.find(tune_key(g, lp, recon, vp) + "/n4");
+    return it == g_tune.end() ? tuned_cfg(g, lp, recon, vp) : it->second;
+}
+
 // ---------------------------------------------------------------------------------------------------
 // Pinned host staging (control block upload, state polls)
 // ---------------------------------------------------------------------------------------------------
@@ -231,7 +237,7 @@ int make_layout(int nsys, const sp_system* systems, const sp_cg_params* prm, int
         const GroupPlan& G = L->groups[big];
         const int lp = prm->inner == SP_F64 ? SP_F64 : G.U->lo_prec;
         const int rc = prm->inner == SP_F64 ? 18 : G.U->recon;
-        L->cfg = tuned_cfg(G.g, lp, rc, prm->inner);
+        L->cfg = n_rhs_max > 1 ? tuned_cfg_batched(G.g, lp, rc, prm->inner) : tuned_cfg(G.g, lp, rc, prm->inner);
         // one system: 256-thread blocks when they admit the fused iteration and the tuned shape does not
         // (the block size moves the operator by a few percent at most, the fused iteration saves a
         // finalize launch per iteration)
@@ -798,36 +804,94 @@ int sp_tune_dslash(const sp_geom* g, const sp_gauge* U, int prec, void* in, void
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
     const int nts[3] = {64, 128, 256};
-    LaunchCfg best;
-    float best_t = 1e30f;
     const int reps = 20;
-    for (int remap = 0; remap <= 1; ++remap)
-        for (int nt : nts) {
-            LaunchCfg c;
-            c.nt = nt;
-            c.remap = remap;
-            const int nb = blocks_for(G.Vh, nt);
-            d.grp.nblk = nb;
-            for (int w = 0; w < 3; ++w)
-                HIP_TRY(launch_dslash(d, nb, c, lp, recon, prec, 1, S_P, S_T, DS_PLAIN, G_NONE, prec == SP_F64, s));
-            HIP_TRY(hipEventRecord(e0, s));
-            for (int k = 0; k < reps; ++k)
-                HIP_TRY(launch_dslash(d, nb, c, lp, recon, prec, 1, S_P, S_T, DS_PLAIN, G_NONE, prec == SP_F64, s));
-            HIP_TRY(hipEventRecord(e1, s));
-            HIP_TRY(hipEventSynchronize(e1));
-            float ms = 0;
-            HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-            ms /= reps;
-            if (ms < best_t) {
-                best_t = ms;
-                best = c;
+    const int use64 = prec == SP_F64;
+    // mean time of `reps` launches after 3 warm-ups, for every block size and block order; the fastest wins
+    auto sweep = [&](auto launch, LaunchCfg* best, float* best_t) -> hipError_t {
+        *best_t = 1e30f;
+        for (int remap = 0; remap <= 1; ++remap)
+            for (int nt : nts) {
+                LaunchCfg c;
+                c.nt = nt;
+                c.remap = remap;
+                hipError_t e;
+                for (int w = 0; w < 3; ++w)
+                    if ((e = launch(c))) return e;
+                if ((e = hipEventRecord(e0, s))) return e;
+                for (int r = 0; r < reps; ++r)
+                    if ((e = launch(c))) return e;
+                if ((e = hipEventRecord(e1, s))) return e;
+                if ((e = hipEventSynchronize(e1))) return e;
+                float ms = 0;
+                if ((e = hipEventElapsedTime(&ms, e0, e1))) return e;
+                ms /= reps;
+                if (ms < *best_t) {
+                    *best_t = ms;
+                    *best = c;
+                }
             }
+        return hipSuccess;
+    };
+    LaunchCfg best, best4;
+    float best_t = 0, best4_t = 0;
+    HIP_TRY(sweep(
+        [&](LaunchCfg c) {
+            const int nb = blocks_for(G.Vh, c.nt);
+            d.grp.nblk = nb;
+            return launch_dslash(d, nb, c, lp, recon, prec, 1, S_P, S_T, DS_PLAIN, G_NONE, use64, s);
+        },
+        &best, &best_t));
+    // The NB-right-hand-side operator of batched solves has its own register use and therefore its own
+    // best shape (key suffix "/n4"). It is timed on NB copies of the input into NB outputs, in a temporary
+    // device buffer that also holds the group and system descriptors; the buffer is freed before return.
+    {
+        const size_t vb = align256((size_t)G.Vh * vec_site_bytes(prec));
+        const size_t gb = align256(sizeof(GroupDev)), sb = align256(NB * sizeof(SysDev));
+        char* buf = nullptr;
+        HIP_TRY(hipMalloc((void**)&buf, 2 * NB * vb + gb + sb));
+        GroupDev hg = {};
+        hg.g = G;
+        hg.links_lo = d.grp.links_lo;
+        hg.links64 = d.grp.links64;
+        hg.nrhs = NB;
+        SysDev hs[NB] = {};
+        hipError_t e = hipSuccess;
+        for (int r = 0; r < NB && !e; ++r) {
+            hs[r].v[S_P] = buf + (size_t)r * vb;
+            hs[r].v[S_T] = buf + (size_t)(NB + r) * vb;
+            e = hipMemcpyAsync(hs[r].v[S_P], in, (size_t)G.Vh * vec_site_bytes(prec), hipMemcpyDeviceToDevice, s);
         }
+        GroupDev* dg = (GroupDev*)(buf + 2 * NB * vb);
+        SysDev* ds = (SysDev*)(buf + 2 * NB * vb + gb);
+        if (!e) e = hipMemcpyAsync(ds, hs, sizeof hs, hipMemcpyHostToDevice, s);
+        DescBatch db;
+        db.grp = dg;
+        db.sys = ds;
+        db.ngroups = 1;
+        if (!e)
+            e = sweep(
+                [&](LaunchCfg c) {
+                    const int nb = blocks_for(G.Vh, c.nt);
+                    if (hg.nblk != nb) {  // the descriptor lives in device memory: rewrite it per shape
+                        hg.nblk = nb;
+                        hipError_t ee = hipMemcpyAsync(dg, &hg, sizeof hg, hipMemcpyHostToDevice, s);
+                        if (!ee) ee = hipStreamSynchronize(s);
+                        if (ee) return ee;
+                    }
+                    return launch_dslash(db, nb, c, lp, recon, prec, 1, S_P, S_T, DS_PLAIN, G_NONE, use64, s);
+                },
+                &best4, &best4_t);
+        const hipError_t es = hipStreamSynchronize(s);
+        (void)hipFree(buf);
+        HIP_TRY(e);
+        HIP_TRY(es);
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     {
         std::lock_guard<std::mutex> lock(g_mu);
         g_tune[tune_key(G, lp, recon, prec)] = best;
+        g_tune[tune_key(G, lp, recon, prec) + "/n4"] = best4;
     }
     if (best_ms) *best_ms = best_t;
     return SP_OK;
