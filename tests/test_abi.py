@@ -104,6 +104,37 @@ def test_npr_sizes_and_validation():
     assert lib.sp_npr_path_links(g, None, F, None) == _lib.SP_ERR_INVALID_ARG
 
 
+def test_geometry_limits_and_degenerate_calls():
+    # all of these fail in the host-side checks, before any device memory is touched
+    lib = _lib.load()
+    geom = lambda d, bc=0: _lib.sp_geom((ctypes.c_int32 * 4)(*d), bc)  # noqa: E731
+    for d in ((3, 4, 4, 4), (4, 4, 4, 0), (4, 4, 4, 1), (4, -2, 4, 4)):
+        assert lib.sp_vec_bytes(ctypes.byref(geom(d)), _lib.SP_F32) == 0
+    # the largest lattice the checkerboard index division supports is V/2 < 2^24
+    big = geom((256, 256, 256, 2))  # V/2 = 2^24
+    assert lib.sp_vec_bytes(ctypes.byref(big), _lib.SP_F32) == 0
+    ok = geom((256, 256, 254, 2))
+    assert lib.sp_vec_bytes(ctypes.byref(ok), _lib.SP_F32) == 256 * 256 * 254 * 24
+    assert lib.sp_vec_bytes(ctypes.byref(geom((4, 4, 4, 4), 2)), _lib.SP_F32) == 0  # bc_t must be 0 or 1
+    F = 1 << 30
+    g = geom((4, 4, 4, 4))
+    assert lib.sp_dslash(ctypes.byref(g), None, _lib.SP_F32, F, F + 4096, 1, None) == _lib.SP_ERR_INVALID_ARG
+    gauge = _lib.sp_gauge(F, F, _lib.SP_F32, 18)
+    assert lib.sp_dslash(ctypes.byref(g), ctypes.byref(gauge), _lib.SP_F32, F, F, 1, None) == _lib.SP_ERR_INVALID_ARG
+    assert lib.sp_dslash(ctypes.byref(g), ctypes.byref(gauge), _lib.SP_F32, F, F + 4096, 2, None) == _lib.SP_ERR_INVALID_ARG
+    prm = _lib.sp_cg_params(1e-8, 100, _lib.SP_F32, 0.1, 0, 25, 0, 1)
+    st = _lib.sp_cg_stats()
+    assert lib.sp_cg_solve_batched(0, None, ctypes.byref(prm), ctypes.byref(st), F, 1 << 30, None) < 0
+    for bad in (_lib.sp_cg_params(0.0, 100, _lib.SP_F32, 0.1, 0, 25, 0, 1),
+                _lib.sp_cg_params(1e-8, 0, _lib.SP_F32, 0.1, 0, 25, 0, 1),
+                _lib.sp_cg_params(1e-8, 100, _lib.SP_F32, 1.5, 0, 25, 0, 1)):
+        rc = lib.sp_cg_solve(ctypes.byref(g), ctypes.byref(gauge), 0.1, F, F + 4096, ctypes.byref(bad),
+                             ctypes.byref(st), F + 8192, 1 << 30, None)
+        assert rc == _lib.SP_ERR_INVALID_ARG, rc
+    assert lib.sp_full_solve(ctypes.byref(g), ctypes.byref(gauge), 0.0, F, F + 4096, ctypes.byref(prm),
+                             ctypes.byref(st), F + 8192, 1 << 30, None) == _lib.SP_ERR_INVALID_ARG
+
+
 def test_tune_cache_roundtrip(tmp_path):
     lib = _lib.load()
     p = tmp_path / "tune.json"
