@@ -1,5 +1,6 @@
 // C-ABI of libstagcg.so: argument checks, workspace layout, the CG drivers (single and batched), hipGraph
-// chunk replay, the launch autotuner and the force entry point.
+// chunk replay, the launch autotuner, and the force, full-lattice solve, HYP smearing and NPR contraction
+// entry points.
 //
 // Solver schedule (mixed precision, after the FP64 set-up r = b - A x0):
 //   chunk = poll_chunk iterations of
@@ -10,7 +11,10 @@
 //           then a reliable update when due (every ru_every iterations, when |r| drops below
 //           delta * |r at the last update|, at apparent convergence and at the iteration cap):
 //             x64 += x_lo, x_lo = 0; r = b - A x64 in FP64; r_lo = round(r); converged if |r| <= tol |b|
-//   The host replays chunks (one hipGraph launch each) and reads the device state once per chunk.
+//   The host replays chunks (one hipGraph launch each) and reads the device state once per chunk. A single
+//   system takes three launches per iteration: alpha and beta (with the stopping decisions) are formed in
+//   every block of the update and p-update launches from the block partials of the launch before. Batched
+//   groups take five: two one-block finalize launches between them.
 // Plain FP64 CG is the same schedule with FP64 vectors, x updated in place and the FP64 true residual
 // computed only at apparent convergence.
 #include <hip/hip_runtime.h>
