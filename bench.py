@@ -410,7 +410,7 @@ def main():
     if not args.no_fp64:
         x64, st64 = solve_fp64()
         torch.cuda.synchronize()
-        per64, (x64, st64) = timed_solves(torch, solve_fp64, max(1, args.steps // 2))
+        per64, (x64, st64) = timed_solves(torch, solve_fp64, max(1, args.steps))
         t_fp64, t_fp64_se = mean_stderr(per64)
         xref, stref = solve_fp64(1e-12)
         err = float(torch.linalg.norm(x - xref) / torch.linalg.norm(xref))
@@ -508,7 +508,7 @@ def main():
                 sp.cg_solve(Gl, mass, b, tol=tol, inner=prec, workspace=ws)
                 torch.cuda.synchronize()
                 pl, (xl, stl) = timed_solves(
-                    torch, lambda: sp.cg_solve(Gl, mass, b, tol=tol, inner=prec, workspace=ws), 5)
+                    torch, lambda: sp.cg_solve(Gl, mass, b, tol=tol, inner=prec, workspace=ws), max(1, args.steps))
                 tl, tl_se = mean_stderr(pl)
                 el = float(torch.linalg.norm(xl - xref) / torch.linalg.norm(xref))
                 low[f"{prec}_r{rc}"] = {"s": tl, "s_stderr": tl_se, "solves": len(pl), "iters": stl.iters,
