@@ -103,3 +103,58 @@ def test_dslash_argument_errors():
     with pytest.raises(sp.StagError) as e:
         sp.pack_vec(odd, torch.zeros((odd.Vh, 3), dtype=torch.complex128, device="cuda:0"), "f32")
     assert e.value.code == -2
+
+
+def _eta(c, mu):
+    return (-1) ** int(sum(c[:mu]))
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_dslash_largest_lattice_point_sources(prec):
+    """Index arithmetic at the size limit (V/2 just below 2^24, where the float-reciprocal division of the
+    checkerboard index is closest to failing): unit links and point sources at lattice corners, boundaries
+    and the last sites, where (D chi)(n) = 1/2 sum_mu eta_mu(n) [chi(n+mu) - chi(n-mu)] is a few +-1/2
+    entries known exactly; every other output must be exactly zero."""
+    dims = (64, 64, 64, 126)
+    X, Y, Z, T = dims
+    V = X * Y * Z * T
+    assert V // 2 < 2 ** 24 and V // 2 > 2 ** 24 - 2 ** 20
+    announce(f"dslash {prec} largest lattice {dims}")
+    lat = sp.Lattice(dims)
+    links = torch.zeros(4, V, 3, 3, dtype=torch.complex128, device="cuda:0")
+    for i in range(3):
+        links[:, :, i, i] = 1.0
+    G = sp.Gauge(lat, links, lo_prec="f32", recon=12)
+    del links
+    L = np.array(dims)
+
+    def lex(c):
+        c = np.asarray(c) % L
+        return int(c[0] + X * (c[1] + Y * (c[2] + Z * c[3])))
+
+    corners = [(0, 0, 0, 0), (X - 1, Y - 1, Z - 1, T - 1), (X - 2, Y - 1, Z - 1, T - 1), (0, Y - 1, 0, T - 1),
+               (X - 1, 0, Z - 1, 0), (31, 17, 40, 63), (X - 1, Y - 1, 0, T - 2)]
+    for out_p in (1, 0):
+        srcs = [c for c in corners if sum(c) % 2 == 1 - out_p]
+        v = torch.zeros(V // 2, 3, dtype=torch.complex128, device="cuda:0")
+        expect = {}
+        for k, c in enumerate(srcs):
+            col = k % 3
+            v[lex(c) >> 1, col] = 1.0
+            for mu in range(4):
+                for sgn in (-1, 1):
+                    n = list(c)
+                    n[mu] += sgn  # n = c + sgn mu: chi(n - sgn mu) = delta, coefficient -sgn/2 eta_mu(n)
+                    n = tuple(int(x) for x in np.asarray(n) % L)
+                    key = (lex(n) >> 1, col)
+                    expect[key] = expect.get(key, 0.0) - 0.5 * sgn * _eta(n, mu)
+        y = sp.dslash(G, v, out_p, prec)
+        torch.cuda.synchronize()
+        idx = torch.tensor([k[0] for k in expect], device="cuda:0")
+        col = torch.tensor([k[1] for k in expect], device="cuda:0")
+        got = to_host(y[idx, col])
+        ref = np.array(list(expect.values()), dtype=complex)
+        assert np.array_equal(got, ref), (out_p, np.max(np.abs(got - ref)))
+        y[idx, col] = 0
+        assert torch.count_nonzero(y).item() == 0
+        del v, y
