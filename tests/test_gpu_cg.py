@@ -125,7 +125,8 @@ def _cfg1_golden():
     return cbs, vals
 
 
-@pytest.mark.parametrize("inner,recon", [("f32", 18), ("f64", 18), ("f32", 12), ("f16", 18), ("bf16", 18)])
+@pytest.mark.parametrize("inner,recon", [("f32", 18), ("f64", 18), ("f32", 12), ("f16", 18), ("bf16", 18),
+                                         ("f16", 12), ("bf16", 12)])
 def test_cfg1_full_size_vs_oracle_samples(inner, recon):
     """20^3x64, m = 0.01, to 1e-8 with the tuned launch the benchmark uses: the solution at the sampled sites
     against the oracle's 1e-12 solution (golden file written by the oracle alone), and the true residual of
@@ -178,3 +179,31 @@ def test_full_system_solve_rejects_zero_mass():
     with pytest.raises(sp.StagError) as e:
         sp.full_solve(G, 0.0, to_dev(li.gaussian_vector(256, 504)))
     assert e.value.code == -1
+
+
+@pytest.mark.parametrize("inner,recon", [("f32", 12), ("f16", 12)])
+def test_control_lattice_true_residual_through_the_operator(inner, recon):
+    """32^3x64 (beyond the Infinity Cache; no fused single-system iteration, so the finalize path runs), solved to
+    1e-8; the true residual |b - A x| / |b| is recomputed with the FP64 half operator entry point, independently of
+    the solver's own reliable-update residual."""
+    dims = (32, 32, 32, 64)
+    announce(f"control lattice {dims} {inner} r{recon}")
+    lat = sp.Lattice(dims)
+    gen = torch.Generator(device="cuda:0")
+    gen.manual_seed(71)
+    V = lat.V
+    lam = torch.from_numpy((li.gell_mann() / 2.0).reshape(8, 9)).to("cuda:0")
+    links = torch.empty(4, V, 3, 3, dtype=torch.complex128, device="cuda:0")
+    for mu in range(4):
+        h = torch.randn(V, 8, generator=gen, device="cuda:0", dtype=torch.float64).to(torch.complex128)
+        links[mu] = torch.linalg.matrix_exp((0.3j) * (h @ lam).reshape(V, 3, 3))
+    b = torch.randn(lat.Vh, 3, dtype=torch.complex128, device="cuda:0", generator=gen)
+    G = sp.Gauge(lat, links, lo_prec=inner, recon=recon)
+    m = 0.01
+    x, st = sp.cg_solve(G, m, b, tol=1e-8, inner=inner)
+    assert st.converged, st
+    t = sp.dslash(G, x, 1, "f64")       # D_oe x
+    Ax = m * m * x - sp.dslash(G, t, 0, "f64")  # m^2 x - D_eo D_oe x
+    res = (torch.linalg.norm(b - Ax) / torch.linalg.norm(b)).item()
+    announce(f"  iters={st.iters} ru={st.reliable_updates} solver resid={st.true_rel_resid:.3e} operator resid={res:.3e}")
+    assert res <= 1.01e-8 and abs(res - st.true_rel_resid) <= 1e-3 * res
