@@ -138,11 +138,13 @@ def test_geometry_limits_and_degenerate_calls():
 def test_tune_cache_roundtrip(tmp_path):
     lib = _lib.load()
     p = tmp_path / "tune.json"
-    p.write_text('{\n  "20x20x20x64/l1/r18/v1": {"nt": 128, "remap": 1}\n}\n')
+    p.write_text('{\n  "20x20x20x64/l1/r18/v1": {"nt": 128, "remap": 1},\n'
+                 '  "20x20x20x64/l1/r18/v1/n4": {"nt": 256, "remap": 0}\n}\n')
     assert lib.sp_tune_load(str(p).encode()) == 0
     q = tmp_path / "out.json"
     assert lib.sp_tune_save(str(q).encode()) == 0
     assert '"20x20x20x64/l1/r18/v1": {"nt": 128, "remap": 1}' in q.read_text()
+    assert '"20x20x20x64/l1/r18/v1/n4": {"nt": 256, "remap": 0}' in q.read_text()
     p.write_text('{"x": {"nt": 100, "remap": 1}}')
     assert lib.sp_tune_load(str(p).encode()) == _lib.SP_ERR_INVALID_ARG
     lib.sp_release_cache()
