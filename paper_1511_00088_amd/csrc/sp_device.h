@@ -133,8 +133,8 @@ struct Real<F64> {
 // wavefront reads 64 consecutive sites with one wide load per plane.
 //   F64 : 3 planes of double2 (one per colour)                                        48 B/site
 //   F32 : plane float4 (colours 0,1) + plane float2 (colour 2)                         24 B/site
-//   F16 : plane uint2 (4 halves: colours 0,1) + plane uint (colour 2) + plane float
-//         norm; stored value = half * norm, norm = max |component| of the site           16 B/site
+//   F16 : one plane uint4 per site: 6 halves (colours 0..2) and the float norm, so one
+//         16-byte load; stored value = half * norm, norm = max |component| of the site   16 B/site
 //   BF16: plane uint2 + plane uint, unscaled                                          12 B/site
 // ------------------------------------------------------------------------------------------------------
 template <int P>
@@ -196,36 +196,44 @@ struct VecFmt16 {
     static constexpr bool scaled = (P == F16);
     static constexpr int bytes = scaled ? 16 : 12;
     __device__ static Vec3<float> load(const void* base, int Vh, int cb) {
-        const uint2* pa = (const uint2*)base;
-        const uint32_t* pb = (const uint32_t*)(pa + Vh);
-        uint2 a = pa[cb];
-        uint32_t b = pb[cb];
+        uint32_t w0, w1, w2;
         float s = 1.0f;
-        if constexpr (scaled) s = ((const float*)(pb + Vh))[cb];
+        if constexpr (scaled) {
+            const uint4 q = ((const uint4*)base)[cb];  // three packed pairs and the site norm: one load
+            w0 = q.x; w1 = q.y; w2 = q.z;
+            s = __uint_as_float(q.w);
+        } else {
+            const uint2* pa = (const uint2*)base;
+            const uint2 a = pa[cb];
+            w0 = a.x; w1 = a.y;
+            w2 = ((const uint32_t*)(pa + Vh))[cb];
+        }
         Vec3<float> v;
-        v.c[0].re = s * unpack_lo<P>(a.x); v.c[0].im = s * unpack_hi<P>(a.x);
-        v.c[1].re = s * unpack_lo<P>(a.y); v.c[1].im = s * unpack_hi<P>(a.y);
-        v.c[2].re = s * unpack_lo<P>(b);   v.c[2].im = s * unpack_hi<P>(b);
+        v.c[0].re = s * unpack_lo<P>(w0); v.c[0].im = s * unpack_hi<P>(w0);
+        v.c[1].re = s * unpack_lo<P>(w1); v.c[1].im = s * unpack_hi<P>(w1);
+        v.c[2].re = s * unpack_lo<P>(w2); v.c[2].im = s * unpack_hi<P>(w2);
         return v;
     }
     __device__ static void store(void* base, int Vh, int cb, const Vec3<float>& v) { (void)store_rt(base, Vh, cb, v); }
     // store and return the value as stored (rounded to 16 bits, scaled by the site norm)
     __device__ static Vec3<float> store_rt(void* base, int Vh, int cb, const Vec3<float>& v) {
-        uint2* pa = (uint2*)base;
-        uint32_t* pb = (uint32_t*)(pa + Vh);
         float inv = 1.0f, m = 1.0f;
         if constexpr (scaled) {
             m = 0.0f;
 #pragma unroll
             for (int c = 0; c < 3; ++c) m = fmaxf(m, fmaxf(fabsf(v.c[c].re), fabsf(v.c[c].im)));
-            ((float*)(pb + Vh))[cb] = m;
             inv = m > 0.0f ? 1.0f / m : 0.0f;
         }
         const uint32_t w0 = pack2<P>(inv * v.c[0].re, inv * v.c[0].im);
         const uint32_t w1 = pack2<P>(inv * v.c[1].re, inv * v.c[1].im);
         const uint32_t w2 = pack2<P>(inv * v.c[2].re, inv * v.c[2].im);
-        pa[cb] = make_uint2(w0, w1);
-        pb[cb] = w2;
+        if constexpr (scaled) {
+            ((uint4*)base)[cb] = make_uint4(w0, w1, w2, __float_as_uint(m));
+        } else {
+            uint2* pa = (uint2*)base;
+            pa[cb] = make_uint2(w0, w1);
+            ((uint32_t*)(pa + Vh))[cb] = w2;
+        }
         Vec3<float> o;
         o.c[0].re = m * unpack_lo<P>(w0); o.c[0].im = m * unpack_hi<P>(w0);
         o.c[1].re = m * unpack_lo<P>(w1); o.c[1].im = m * unpack_hi<P>(w1);
