@@ -343,6 +343,23 @@ hipError_t enqueue_iterations_fused(const DescSingle& d0, const Plan& pl, int co
     const int use64 = pl.inner == SP_F64;
     DescSingle d[2] = {d0, d0};
     d[1].sys.st = d0.sys.st + 1;
+    if (pl.inner == SP_F32 || pl.inner == SP_F64) {
+        // two launches per iteration (t and p by recurrence in k_norm_rec); the chunk's last p update is
+        // k_xpay_fused, so the next chunk starts from a p and t that the chunk boundary leaves consistent
+        for (int i = 0; i < count; ++i) {
+            hipError_t e;
+            if ((e = launch_norm_rec(d[i & 1], d[(i + 1) & 1].sys.st, pl.nblocks, pl.cfg, pl.lp, pl.recon, pl.inner,
+                                     s)))
+                return e;
+            if ((e = launch_dslash(d[(i + 1) & 1], pl.nblocks, pl.cfg, pl.lp, pl.recon, pl.inner, 0, S_T, S_R,
+                                   DS_UPDATE_FUSED, G_ITER, use64, s)))
+                return e;
+        }
+        hipError_t e = launch_xpay_fused(d[count & 1], d[(count + 1) & 1].sys.st, 1, pl.nblocks, pl.cfg, pl.inner, s);
+        if (e) return e;
+        if ((count + 1) & 1) return launch_state_copy(d[1].sys.st, d[0].sys.st, s);
+        return hipSuccess;
+    }
     for (int i = 0; i < count; ++i) {
         const DescSingle& di = d[i & 1];
         hipError_t e;

@@ -438,13 +438,13 @@ __host__ __device__ __forceinline__ float eta_sign(const Site& s, int mu) {
 // the backward link U_mu(n-mu) sits at the neighbour's cb in the parity 1-p block.
 // ------------------------------------------------------------------------------------------------------
 template <int LP, int RECON, int VP>
-__device__ __forceinline__ Vec3<typename Real<VP>::T> dslash_site(const Geom& g, const void* links, const void* in,
-                                                                  int p, const Site& s) {
+__device__ __forceinline__ Vec3<typename Real<VP>::T> dslash_site(const Geom g, const void* links, const void* in,
+                                                                  int p, const Site s) {
     using R = typename Real<VP>::T;
     using LF = LinkFmt<LP, RECON>;
     using VF = VecFmt<VP>;
     Vec3<R> acc = vzero<R>();
-#pragma unroll
+#pragma unroll((VP == F64 || (LP == F32 && RECON == 12)) ? 2 : 4)
     for (int mu = 0; mu < 4; ++mu) {
         R e = (R)eta_sign(s, mu);
         R sf = e, sb = e;
@@ -513,6 +513,7 @@ enum : int {
     ST_STALL = 16,      // true residual stopped improving
     ST_CONVERGED = 32,  // true residual <= tol |b|
     ST_XPAY_DUE = 64,   // p = a r + beta p is due (after a reliable update, or p = r at the start)
+    ST_T_STALE = 128,   // p was formed outside the t recurrence: the next t must be D_oe p itself
 };
 
 struct alignas(64) SolverState {
@@ -611,7 +612,7 @@ __device__ __forceinline__ void fin_resid(SolverState* st, double rho_true, doub
             st->xpay_a = 1.0 - beta * (rp / rho_true);
         }
     }
-    st->flags |= ST_XPAY_DUE;
+    st->flags |= ST_XPAY_DUE | ST_T_STALE;
     st->rho = rho_true;
 }
 

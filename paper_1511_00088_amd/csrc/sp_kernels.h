@@ -463,6 +463,7 @@ __global__ __launch_bounds__(256) void k_xpay_fused(DescSingle d, SolverState* _
             fin_alpha(&s, G.rec[0]);
             if (!(s.flags & ST_DONE)) fin_update(&s, part[0], chunk_end != 0);
             go = !(s.flags & (ST_DONE | ST_PENDING));
+            if (go) s.flags |= ST_T_STALE;  // p formed here: a following k_norm_rec applies D_oe to it
         }
         if (gblk == 0) *st_out = s;
         beta_sh = s.beta;
@@ -484,6 +485,92 @@ __global__ __launch_bounds__(256) void k_xpay_fused(DescSingle d, SolverState* _
             dots[0] += (double)ps.c[i].re * (double)ps.c[i].re + (double)ps.c[i].im * (double)ps.c[i].im;
     }
     block_partials<1>(G.partials_p, gblk, dots);
+}
+
+// The first launch of an iteration of one system in FP32 or FP64 (with DS_UPDATE_FUSED the second). It
+// replaces the p update and t = D_oe p of the three-launch iteration by the recurrence
+//   p_i = r_i + beta p_{i-1},   t_i = D_oe p_i = D_oe r_i + beta t_{i-1},
+// so that the operator is applied to r_i, which is complete when the launch starts, while p_i is formed in
+// the same launch (each thread also updates the even site with its own index). Every block first takes the
+// decisions of the last update from its |r|^2 partials (as k_xpay_fused does); block 0 writes the advanced
+// state to st_out. When p was formed elsewhere (start, reliable update, end of the last chunk: ST_T_STALE)
+// the launch applies D_oe to p directly and takes no decision. Partials: Re<D_oe in, t> as DS_NORM, and
+// |p_i|^2 from the recurrence (the other paths leave the |p|^2 partials of the launch that formed p).
+template <int LP, int RECON, int VP>
+__global__ __launch_bounds__(256) void k_norm_rec(DescSingle d, SolverState* __restrict__ st_out, int remap) {
+    using R = typename Real<VP>::T;
+    using VF = VecFmt<VP>;
+    const int gblk = logical_block(remap);
+    const GroupDev& G = d.grp;
+    const SysDev& S = d.sys;
+    const SolverState* st = S.st;
+    const Geom g = G.g;
+    const int cb = gblk * blockDim.x + threadIdx.x;
+    const bool live = cb < g.Vh;
+    const int flags = st->flags;
+    if (flags & (ST_DONE | ST_PENDING)) {
+        if (gblk == 0 && threadIdx.x == 0) *st_out = *st;
+        return;
+    }
+    const bool direct = (flags & ST_T_STALE) != 0;
+    double part[1] = {0.0};
+    if (!direct)
+        for (int b = threadIdx.x; b < G.nblk; b += blockDim.x) part[0] += G.partials_r[b];
+    Vec3<R> acc = vzero<R>(), told = vzero<R>(), rv = vzero<R>(), pv = vzero<R>();
+    if (live) {
+        acc = dslash_site<LP, RECON, VP>(g, G.links_lo, direct ? S.v[S_P] : S.v[S_R], 1, site_of(g, 1, cb));
+        if (!direct) {
+            told = VF::load(S.v[S_T], g.Vh, cb);
+            rv = VF::load(S.v[S_R], g.Vh, cb);
+            pv = VF::load(S.v[S_P], g.Vh, cb);
+        }
+    }
+    __shared__ double beta_sh;
+    __shared__ int go_sh;
+    if (!direct) block_sum<1>(part);
+    if (threadIdx.x == 0) {
+        SolverState s = *st;
+        bool go = true;
+        if (direct) {
+            s.flags &= ~ST_T_STALE;
+        } else {
+            fin_alpha(&s, G.rec[0]);
+            if (!(s.flags & ST_DONE)) fin_update(&s, part[0], false);
+            go = !(s.flags & (ST_DONE | ST_PENDING));
+        }
+        if (gblk == 0) *st_out = s;
+        beta_sh = direct ? 0.0 : s.beta;
+        go_sh = go;
+    }
+    __syncthreads();
+    if (!go_sh) return;  // paused or stopped: t, p and their partials stay as they are
+    const R beta = (R)beta_sh;
+    double dots[2] = {0.0, 0.0};
+    if (live) {
+        Vec3<R> t = acc;
+        if (!direct) {
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                t.c[i].re += beta * told.c[i].re;
+                t.c[i].im += beta * told.c[i].im;
+                pv.c[i].re = rv.c[i].re + beta * pv.c[i].re;
+                pv.c[i].im = rv.c[i].im + beta * pv.c[i].im;
+            }
+            const Vec3<R> ps = VF::store_rt(S.v[S_P], g.Vh, cb, pv);
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+                dots[1] += (double)ps.c[i].re * (double)ps.c[i].re + (double)ps.c[i].im * (double)ps.c[i].im;
+        }
+        const Vec3<R> ts = VF::store_rt(S.v[S_T], g.Vh, cb, t);
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+            dots[0] += (double)t.c[i].re * (double)ts.c[i].re + (double)t.c[i].im * (double)ts.c[i].im;
+    }
+    block_sum<2>(dots);
+    if (threadIdx.x == 0) {
+        G.partials[gblk] = dots[0];
+        if (!direct) G.partials_p[gblk] = dots[1];
+    }
 }
 
 // x64 += xlo; xlo = 0 (reliable update).

@@ -45,6 +45,20 @@ hipError_t launch_dslash(const D& d, int nblocks, LaunchCfg c, int lp, int recon
     return hipErrorInvalidValue;
 }
 
+hipError_t launch_norm_rec(const DescSingle& d, SolverState* st_out, int nblocks, LaunchCfg c, int lp, int recon, int vp,
+                           hipStream_t s) {
+#define SP_LAUNCH(LP, RC, VP)                                                                              \
+    do {                                                                                                   \
+        hipLaunchKernelGGL((k_norm_rec<LP, RC, VP>), dim3(nblocks), dim3(c.nt), 0, s, d, st_out, c.remap);  \
+        return hipGetLastError();                                                                          \
+    } while (0)
+    if (lp == F64 && recon == 18 && vp == F64) SP_LAUNCH(F64, 18, F64);
+    if (lp == F32 && recon == 18 && vp == F32) SP_LAUNCH(F32, 18, F32);
+    if (lp == F32 && recon == 12 && vp == F32) SP_LAUNCH(F32, 12, F32);
+#undef SP_LAUNCH
+    return hipErrorInvalidValue;
+}
+
 template <class D>
 hipError_t launch_resid(const D& d, int nblocks, LaunchCfg c, int op, int init, hipStream_t s) {
     constexpr int N = NOf<D>::value;
