@@ -76,8 +76,8 @@ typedef struct {
  *  inner      precision of the iterated vectors and links: SP_F64 gives plain FP64 CG; SP_F32, SP_F16,
  *             SP_BF16 give mixed precision with FP64 reliable updates (true residual recomputed from an
  *             FP64 solution that accumulates the low-precision increments)
- *  delta      reliable update when |r_iterated| < delta * |r at the last update| (0 disables; checked at
- *             the end of each poll chunk)
+ *  delta      reliable update when |r_iterated| < delta * |r at the last update| (0 disables; ignored
+ *             for SP_F64; checked at the end of each poll chunk)
  *  ru_every   reliable update at least every ru_every iterations (ignored for SP_F64; <= 0 picks 100;
  *             checked at the end of each poll chunk)
  *  poll_chunk iterations per device-side chunk (one hipGraph launch) between host convergence polls

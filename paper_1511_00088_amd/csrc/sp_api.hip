@@ -481,7 +481,8 @@ SolverState initial_state(const sp_system& s, const sp_cg_params* prm) {
     SolverState st;
     memset(&st, 0, sizeof st);
     st.tol2 = prm->tol * prm->tol;
-    st.delta2 = prm->delta > 0 ? prm->delta * prm->delta : 0.0;
+    // plain FP64 CG recomputes the true residual only when the iterated one says it has converged
+    st.delta2 = (prm->delta > 0 && prm->inner != SP_F64) ? prm->delta * prm->delta : 0.0;
     st.m2 = s.mass * s.mass;
     st.max_iter = prm->max_iter;
     int every = prm->ru_every;
