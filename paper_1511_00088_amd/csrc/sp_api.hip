@@ -379,9 +379,9 @@ hipError_t enqueue_iterations_fused(const DescSingle& d0, const Plan& pl, int co
 // Reliable update (runs only for systems whose last iteration requested it): x64 += x_lo; t64 = D_oe x64;
 // r = b - A x64 in FP64 (|r|^2, Re<r,p>) -> state; p = a r + beta p.
 template <class D>
-hipError_t enqueue_reliable(const D& d, const Plan& pl, hipStream_t s) {
+hipError_t enqueue_reliable(const D& d, const Plan& pl, bool accum_done, hipStream_t s) {
     hipError_t e;
-    if (pl.inner != SP_F64 && (e = launch_accum(d, pl.nblocks, pl.cfg, s))) return e;
+    if (pl.inner != SP_F64 && !accum_done && (e = launch_accum(d, pl.nblocks, pl.cfg, s))) return e;
     if ((e = launch_dslash(d, pl.nblocks, pl.cfg, SP_F64, 18, SP_F64, 1, S_X64, S_T64, DS_PLAIN, G_RU, 1, s)))
         return e;
     if ((e = launch_resid(d, pl.nblocks, pl.cfg, pl.inner, 0, s))) return e;
@@ -405,12 +405,14 @@ hipError_t enqueue_setup(const D& d, const Plan& pl, hipStream_t s) {
 template <class D>
 hipError_t enqueue_chunk(const D& d, const Plan& pl, int iters, hipStream_t s) {
     hipError_t e;
+    // the fused iteration's chunk-end k_xpay_fused already folds x_lo into x64 when an update is due
+    const bool fused = fused_single<D>(pl);
     if constexpr (std::is_same<D, DescSingle>::value)
-        e = fused_single<D>(pl) ? enqueue_iterations_fused(d, pl, iters, s) : enqueue_iterations(d, pl, iters, s);
+        e = fused ? enqueue_iterations_fused(d, pl, iters, s) : enqueue_iterations(d, pl, iters, s);
     else
         e = enqueue_iterations(d, pl, iters, s);
     if (e) return e;
-    return enqueue_reliable(d, pl, s);
+    return enqueue_reliable(d, pl, fused, s);
 }
 
 // ---------------------------------------------------------------------------------------------------

@@ -455,7 +455,7 @@ __global__ __launch_bounds__(256) void k_xpay_fused(DescSingle d, SolverState* _
     }
     block_sum<1>(part);
     __shared__ double beta_sh;
-    __shared__ int go_sh;
+    __shared__ int go_sh, ru_sh;
     if (threadIdx.x == 0) {
         SolverState s = *st;
         bool go = false;
@@ -468,8 +468,26 @@ __global__ __launch_bounds__(256) void k_xpay_fused(DescSingle d, SolverState* _
         if (gblk == 0) *st_out = s;
         beta_sh = s.beta;
         go_sh = go;
+        ru_sh = chunk_end != 0 && (s.flags & ST_PENDING) && !(s.flags & ST_DONE);
     }
     __syncthreads();
+    if constexpr (VP != F64) {
+        if (ru_sh) {
+            // the reliable update that follows the chunk starts here: x64 += x_lo; x_lo = 0 (k_accum's step)
+            if (live) {
+                Vec3<double> x = VecFmt<F64>::load(d.sys.v[S_X64], Vh, cb);
+                const Vec3<float> xl = VecFmt<F32>::load(d.sys.v[S_XLO], Vh, cb);
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    x.c[i].re += (double)xl.c[i].re;
+                    x.c[i].im += (double)xl.c[i].im;
+                }
+                VecFmt<F64>::store(d.sys.v[S_X64], Vh, cb, x);
+                VecFmt<F32>::store(d.sys.v[S_XLO], Vh, cb, vzero<float>());
+            }
+            return;
+        }
+    }
     if (!go_sh) return;  // paused or stopped: p and its partials stay as they are
     const R beta = (R)beta_sh;
     double dots[1] = {0.0};
