@@ -12,9 +12,12 @@
 //           delta * |r at the last update|, at apparent convergence and at the iteration cap):
 //             x64 += x_lo, x_lo = 0; r = b - A x64 in FP64; r_lo = round(r); converged if |r| <= tol |b|
 //   The host replays chunks (one hipGraph launch each) and reads the device state once per chunk. A single
-//   system takes three launches per iteration: alpha and beta (with the stopping decisions) are formed in
-//   every block of the update and p-update launches from the block partials of the launch before. Batched
-//   groups take five: two one-block finalize launches between them.
+//   system in FP32 or FP64 takes two launches per iteration: beta (with the stopping decisions), the p
+//   update and t = D_oe r + beta t (the recurrence of t = D_oe p) in one, alpha and the x and r updates in
+//   the other, each block forming the scalars from the block partials of the launch before; the chunk
+//   ends with a p update alone, after which t is formed from p directly. With 16-bit storage a single
+//   system takes three (t = D_oe p, the update, the p update), and batched groups take five: two one-block
+//   finalize launches between them.
 // Plain FP64 CG is the same schedule with FP64 vectors, x updated in place and the FP64 true residual
 // computed only at apparent convergence.
 #include <hip/hip_runtime.h>
@@ -309,8 +312,9 @@ struct Plan {
 };
 
 // One system with at most four partials per thread: every block of the update forms alpha itself and
-// every block of the p update forms beta and the stopping decisions itself, so an iteration is three
-// launches with no finalize (k_dslash DS_UPDATE_FUSED, k_xpay_fused).
+// every block of the launch that updates p forms beta and the stopping decisions itself, so no finalize
+// launch is needed (FP32/FP64: k_norm_rec, k_dslash DS_UPDATE_FUSED; 16-bit: k_dslash DS_NORM,
+// DS_UPDATE_FUSED, k_xpay_fused).
 template <class D>
 bool fused_single(const Plan& pl) {
     return std::is_same<D, DescSingle>::value && pl.nblocks <= FUSED_PARTIALS * pl.cfg.nt;

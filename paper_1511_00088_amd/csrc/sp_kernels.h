@@ -433,7 +433,8 @@ __global__ __launch_bounds__(256) void k_xpay(D d, int gate, int remap) {
 // takes the decisions of the update finalize itself (breakdown, convergence and reliable-update triggers,
 // beta), then p = r + beta p with |p|^2 partials. The state is double-buffered: all blocks read st_in
 // (the descriptor's state) and block 0 writes the advanced state to st_out, which the next iteration's
-// launches read, so no block can see a half-written state.
+// launches read, so no block can see a half-written state. At a chunk end (chunk_end != 0) with a reliable
+// update due, the launch instead performs the update's first step, x64 += x_lo and x_lo = 0.
 template <int VP>
 __global__ __launch_bounds__(256) void k_xpay_fused(DescSingle d, SolverState* __restrict__ st_out, int chunk_end,
                                                      int remap) {
