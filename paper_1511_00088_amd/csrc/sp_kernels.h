@@ -59,10 +59,17 @@ struct DescBatch {
 
 // --- descriptor access ---------------------------------------------------------------------------------
 __device__ __forceinline__ int find_group(const DescSingle&, int) { return 0; }
+// The group of a logical block: the number of groups that start at or before it, minus one (group starts
+// increase strictly). Lane l tests group l (then l + 64, ...), so the starts load in parallel instead of
+// one after the other. Called by whole waves at kernel entry.
 __device__ __forceinline__ int find_group(const DescBatch& d, int lblk) {
-    int g = 0;
-    while (g + 1 < d.ngroups && lblk >= d.grp[g + 1].blk0) ++g;
-    return g;
+    int count = 0;
+    for (int g0 = 0; g0 < d.ngroups; g0 += 64) {
+        const int g = g0 + (int)(threadIdx.x & 63);
+        const bool started = g < d.ngroups && d.grp[g].blk0 <= lblk;
+        count += __popcll(__ballot(started));
+    }
+    return __builtin_amdgcn_readfirstlane(count - 1);
 }
 __device__ __forceinline__ const GroupDev& grp_of(const DescSingle& d, int) { return d.grp; }
 __device__ __forceinline__ const GroupDev& grp_of(const DescBatch& d, int g) { return d.grp[g]; }
@@ -78,9 +85,9 @@ __device__ __forceinline__ int logical_block(int remap) {
     return x * q + min(x, rem) + i;
 }
 
-__device__ __forceinline__ bool gate_open(const SolverState* st, int gate) {
-    if (gate == G_NONE || st == nullptr) return true;
-    const int f = st->flags;
+// Whether a launch gated by `gate` works on a system whose state flags are f.
+__device__ __forceinline__ bool gate_flags_open(int f, int gate) {
+    if (gate == G_NONE) return true;
     if (f & ST_DONE) return false;
     if (gate == G_ITER) return !(f & ST_PENDING);
     if (gate == G_RU) return (f & ST_PENDING) != 0;
@@ -96,18 +103,26 @@ struct Rhs {
     bool any;
 };
 
+// The state pointers and flags of the group's systems load unconditionally (slots beyond the group's count
+// repeat its first system and are marked inactive), so the loads of all systems are in flight together.
 template <int N, class D>
 __device__ __forceinline__ Rhs<N> rhs_of(const D& d, const GroupDev& G, int gate) {
     Rhs<N> h;
+    if constexpr (N == 1) {
+        h.st[0] = sys_of(d, G.sys0).st;
+        h.act[0] = G.nrhs > 0 && (gate == G_NONE || h.st[0] == nullptr || gate_flags_open(h.st[0]->flags, gate));
+        h.any = h.act[0];
+        return h;
+    }
     h.any = false;
 #pragma unroll
+    for (int r = 0; r < N; ++r) h.st[r] = sys_of(d, G.sys0 + (r < G.nrhs ? r : 0)).st;
+    int f[N];
+#pragma unroll
+    for (int r = 0; r < N; ++r) f[r] = (gate == G_NONE || h.st[r] == nullptr) ? 0 : h.st[r]->flags;
+#pragma unroll
     for (int r = 0; r < N; ++r) {
-        h.act[r] = false;
-        h.st[r] = nullptr;
-        if (r < G.nrhs) {
-            h.st[r] = sys_of(d, G.sys0 + r).st;
-            h.act[r] = gate_open(h.st[r], gate);
-        }
+        h.act[r] = r < G.nrhs && (h.st[r] == nullptr || gate_flags_open(f[r], gate));
         h.any |= h.act[r];
     }
     return h;
