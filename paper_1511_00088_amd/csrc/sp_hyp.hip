@@ -202,8 +202,133 @@ __device__ __forceinline__ void su2_step(M3& x, const M3& w, int i, int j) {
     }
 }
 
+// (m + m^dag) / 2
+__device__ __forceinline__ void hermitize(M3& m) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        m.e[i][i].im = 0.0;
+#pragma unroll
+        for (int j = i + 1; j < 3; ++j) {
+            const C a = m.e[i][j], b = m.e[j][i];
+            m.e[i][j] = {0.5 * (a.re + b.re), 0.5 * (a.im - b.im)};
+            m.e[j][i] = {m.e[i][j].re, -m.e[i][j].im};
+        }
+    }
+}
+
+// I c + a
+__device__ __forceinline__ M3 plus_diag(const M3& a, C c) {
+    M3 r = a;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) r.e[i][i] = cadd(r.e[i][i], c);
+    return r;
+}
+
+// The maximiser of Re tr(X^dag W) over SU(3) without iterating, where it is safe. With W = up H (up the
+// unitary polar factor, det up = e^{i phi}, H = up^dag W Hermitian positive definite) the maximiser is
+// X = up exp(i Theta), Theta = asin(mu G) with G = H^-1: in the eigenbasis of H the problem separates into
+// one phase theta_k per eigenvalue h_k, maximising sum h_k cos theta_k subject to sum theta_k = -phi, whose
+// stationarity condition h_k sin theta_k = mu gives theta_k = asin(mu / h_k); mu follows from
+// tr Theta = -phi. No eigenvectors are formed: the traces tr G^k come from Newton's identities, Theta from
+// the arcsine series in mu G (terms to (mu G)^13) and exp(i Theta) from its Taylor series (to order 8).
+// Used only when |mu| |G|_F <= 0.06, where the first omitted terms are below 1e-17 and the principal
+// phases are the maximum; returns false otherwise, and the caller iterates instead.
+__device__ __forceinline__ bool proj_series(const M3& w, const M3& up, M3& x) {
+    constexpr double c[7] = {1.0, 1.0 / 6, 3.0 / 40, 5.0 / 112, 35.0 / 1152, 63.0 / 2816, 231.0 / 13312};
+    const C du = det3(up);
+    const double phi = atan2(du.im, du.re);
+    M3 h = mul_dn(up, w);
+    hermitize(h);
+    M3 cof;
+    cross(h.e[1], h.e[2], cof.e[0]);
+    cross(h.e[2], h.e[0], cof.e[1]);
+    cross(h.e[0], h.e[1], cof.e[2]);
+    const double dh = h.e[0][0].re * cof.e[0][0].re - h.e[0][0].im * cof.e[0][0].im +
+                      h.e[0][1].re * cof.e[0][1].re - h.e[0][1].im * cof.e[0][1].im +
+                      h.e[0][2].re * cof.e[0][2].re - h.e[0][2].im * cof.e[0][2].im;  // real for Hermitian h
+    if (!(dh > 0.0) || !isfinite(dh)) return false;
+    const double rd = 1.0 / dh;
+    M3 g;  // H^-1 = cof^T / det
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) g.e[i][j] = {cof.e[j][i].re * rd, cof.e[j][i].im * rd};
+    hermitize(g);
+    // power sums p_k = tr G^k: p1, p2 from the entries, then e1 p_{k-1} - e2 p_{k-2} + e3 p_{k-3}
+    double p[14];
+    p[1] = g.e[0][0].re + g.e[1][1].re + g.e[2][2].re;
+    p[2] = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) p[2] += g.e[i][j].re * g.e[i][j].re + g.e[i][j].im * g.e[i][j].im;
+    const double e1 = p[1], e2 = 0.5 * (p[1] * p[1] - p[2]), e3 = rd;
+    p[3] = e1 * p[2] - e2 * p[1] + 3.0 * e3;
+#pragma unroll
+    for (int q = 4; q < 14; ++q) p[q] = e1 * p[q - 1] - e2 * p[q - 2] + e3 * p[q - 3];
+    // tr asin(mu G) = -phi by Newton's method on the series
+    double mu = -phi / p[1];
+#pragma unroll
+    for (int it = 0; it < 6; ++it) {
+        const double m2 = mu * mu;
+        double f = 0.0, df = 0.0, mp = 1.0;  // mp = mu^(2n)
+#pragma unroll
+        for (int n = 0; n < 7; ++n) {
+            df += c[n] * (2 * n + 1) * p[2 * n + 1] * mp;
+            f += c[n] * p[2 * n + 1] * mp * mu;
+            mp *= m2;
+        }
+        mu -= (f + phi) / df;
+    }
+    if (!(fabs(mu) * sqrt(p[2]) <= 0.06)) return false;
+    // Theta = mu G (c0 + K (c1 + K (... c6))), K = mu^2 G^2
+    M3 kk = mul(g, g);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            kk.e[i][j].re *= mu * mu;
+            kk.e[i][j].im *= mu * mu;
+        }
+    M3 a;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) a.e[i][j] = {i == j ? c[6] : 0.0, 0.0};
+#pragma unroll
+    for (int n = 5; n >= 0; --n) a = plus_diag(mul(kk, a), {c[n], 0.0});
+    M3 ith = mul(g, a);  // then i mu: i Theta
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) ith.e[i][j] = {-mu * ith.e[i][j].im, mu * ith.e[i][j].re};
+    // exp(i Theta) = I + i Theta (I + i Theta / 2 (... (I + i Theta / 8)))
+    M3 e;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) e.e[i][j] = {i == j ? 1.0 : 0.0, 0.0};
+#pragma unroll
+    for (int q = 8; q >= 1; --q) {
+        M3 t = mul(ith, e);
+        const double rq = 1.0 / q;
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                t.e[i][j].re *= rq;
+                t.e[i][j].im *= rq;
+            }
+        e = plus_diag(t, {1.0, 0.0});
+    }
+    x = mul(up, e);
+    return true;
+}
+
 __device__ __forceinline__ M3 proj_su3(const M3& w) {
     M3 x = polar_factor(w);
+    M3 y;
+    if (proj_series(w, x, y)) return y;
     const C d = det3(x);
     const double th = -atan2(d.im, d.re) / 3.0;
     const C ph = {cos(th), sin(th)};
