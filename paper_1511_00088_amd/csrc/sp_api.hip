@@ -202,8 +202,6 @@ size_t sys_block_bytes(int Vh, int inner, size_t slot_off[NSLOT]) {
     return off;
 }
 
-int params_inner(const sp_cg_params* prm) { return prm->inner; }
-
 // Groups systems and computes the workspace layout. n_rhs_max: 1 for a single solve, NB for batches.
 int make_layout(int nsys, const sp_system* systems, const sp_cg_params* prm, int n_rhs_max, Layout* L) {
     if (nsys <= 0 || !systems) return fail(SP_ERR_INVALID_ARG, "no systems");
@@ -949,7 +947,6 @@ int sp_tune_load(const char* path) {
     const std::string txt = ss.str();
     std::lock_guard<std::mutex> lock(g_mu);
     size_t pos = 0;
-    int n = 0;
     while ((pos = txt.find('"', pos)) != std::string::npos) {
         const size_t end = txt.find('"', pos + 1);
         if (end == std::string::npos) break;
@@ -964,7 +961,6 @@ int sp_tune_load(const char* path) {
         c.nt = nt;
         c.remap = remap ? 1 : 0;
         g_tune[key] = c;
-        ++n;
         pos = txt.find('}', brace) + 1;
     }
     return SP_OK;

@@ -444,7 +444,8 @@ __device__ __forceinline__ Vec3<typename Real<VP>::T> dslash_site(const Geom g, 
     using LF = LinkFmt<LP, RECON>;
     using VF = VecFmt<VP>;
     Vec3<R> acc = vzero<R>();
-#pragma unroll((VP == F64 || (LP == F32 && RECON == 12)) ? 2 : 4)
+    constexpr int UNROLL = (VP == F64 || (LP == F32 && RECON == 12)) ? 2 : 4;
+#pragma unroll UNROLL
     for (int mu = 0; mu < 4; ++mu) {
         R e = (R)eta_sign(s, mu);
         R sf = e, sb = e;
