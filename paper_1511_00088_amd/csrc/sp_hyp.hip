@@ -217,21 +217,14 @@ __device__ __forceinline__ void hermitize(M3& m) {
     }
 }
 
-// I c + a
-__device__ __forceinline__ M3 plus_diag(const M3& a, C c) {
-    M3 r = a;
-#pragma unroll
-    for (int i = 0; i < 3; ++i) r.e[i][i] = cadd(r.e[i][i], c);
-    return r;
-}
-
 // The maximiser of Re tr(X^dag W) over SU(3) without iterating, where it is safe. With W = up H (up the
 // unitary polar factor, det up = e^{i phi}, H = up^dag W Hermitian positive definite) the maximiser is
 // X = up exp(i Theta), Theta = asin(mu G) with G = H^-1: in the eigenbasis of H the problem separates into
 // one phase theta_k per eigenvalue h_k, maximising sum h_k cos theta_k subject to sum theta_k = -phi, whose
 // stationarity condition h_k sin theta_k = mu gives theta_k = asin(mu / h_k); mu follows from
 // tr Theta = -phi. No eigenvectors are formed: the traces tr G^k come from Newton's identities, Theta from
-// the arcsine series in mu G (terms to (mu G)^13) and exp(i Theta) from its Taylor series (to order 8).
+// the arcsine series in mu G (terms to (mu G)^13) and exp(i Theta) from its Taylor series (to order 8), both
+// as polynomials in G reduced to degree two by the characteristic polynomial.
 // Used only when |mu| |G|_F <= 0.06, where the first omitted terms are below 1e-17 and the principal
 // phases are the maximum; returns false otherwise, and the caller iterates instead.
 __device__ __forceinline__ bool proj_series(const M3& w, const M3& up, M3& x) {
@@ -282,46 +275,59 @@ __device__ __forceinline__ bool proj_series(const M3& w, const M3& up, M3& x) {
         mu -= (f + phi) / df;
     }
     if (!(fabs(mu) * sqrt(p[2]) <= 0.06)) return false;
-    // Theta = mu G (c0 + K (c1 + K (... c6))), K = mu^2 G^2
-    M3 kk = mul(g, g);
+    // Every power series in G reduces to a0 I + a1 G + a2 G^2 (Cayley-Hamilton: G^3 = e1 G^2 - e2 G + e3),
+    // so Theta and exp(i Theta) are carried as three scalar coefficients each; G^2 is the only matrix
+    // product before the last one.
+    double gp[3] = {0.0, 1.0, 0.0};  // G^(2n+1)
+    double th[3] = {0.0, 0.0, 0.0};  // Theta
+    double mp = mu;
 #pragma unroll
-    for (int i = 0; i < 3; ++i)
+    for (int n = 0; n < 7; ++n) {
 #pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            kk.e[i][j].re *= mu * mu;
-            kk.e[i][j].im *= mu * mu;
+        for (int q = 0; q < 3; ++q) th[q] += c[n] * mp * gp[q];
+#pragma unroll
+        for (int rep = 0; rep < 2; ++rep) {  // times G
+            const double a0 = gp[0], a1 = gp[1], a2 = gp[2];
+            gp[0] = a2 * e3;
+            gp[1] = a0 - a2 * e2;
+            gp[2] = a1 + a2 * e1;
         }
-    M3 a;
+        mp *= mu * mu;
+    }
+    // exp(i Theta) = 1 + i Theta (1 + i Theta / 2 (... (1 + i Theta / 8))), products reduced mod the
+    // characteristic polynomial
+    C ev[3] = {{1.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
 #pragma unroll
-    for (int i = 0; i < 3; ++i)
+    for (int q = 8; q >= 1; --q) {
+        C cc[5] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
 #pragma unroll
-        for (int j = 0; j < 3; ++j) a.e[i][j] = {i == j ? c[6] : 0.0, 0.0};
+        for (int a = 0; a < 3; ++a)
 #pragma unroll
-    for (int n = 5; n >= 0; --n) a = plus_diag(mul(kk, a), {c[n], 0.0});
-    M3 ith = mul(g, a);  // then i mu: i Theta
+            for (int b = 0; b < 3; ++b) {  // (i th_a) ev_b
+                cc[a + b].re -= th[a] * ev[b].im;
+                cc[a + b].im += th[a] * ev[b].re;
+            }
 #pragma unroll
-    for (int i = 0; i < 3; ++i)
+        for (int kk = 4; kk >= 3; --kk) {
+            cc[kk - 1] = {cc[kk - 1].re + cc[kk].re * e1, cc[kk - 1].im + cc[kk].im * e1};
+            cc[kk - 2] = {cc[kk - 2].re - cc[kk].re * e2, cc[kk - 2].im - cc[kk].im * e2};
+            cc[kk - 3] = {cc[kk - 3].re + cc[kk].re * e3, cc[kk - 3].im + cc[kk].im * e3};
+        }
+        const double rq = 1.0 / q;
 #pragma unroll
-        for (int j = 0; j < 3; ++j) ith.e[i][j] = {-mu * ith.e[i][j].im, mu * ith.e[i][j].re};
-    // exp(i Theta) = I + i Theta (I + i Theta / 2 (... (I + i Theta / 8)))
+        for (int a = 0; a < 3; ++a) ev[a] = {cc[a].re * rq, cc[a].im * rq};
+        ev[0].re += 1.0;
+    }
+    const M3 g2 = mul(g, g);
     M3 e;
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
-        for (int j = 0; j < 3; ++j) e.e[i][j] = {i == j ? 1.0 : 0.0, 0.0};
-#pragma unroll
-    for (int q = 8; q >= 1; --q) {
-        M3 t = mul(ith, e);
-        const double rq = 1.0 / q;
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-#pragma unroll
-            for (int j = 0; j < 3; ++j) {
-                t.e[i][j].re *= rq;
-                t.e[i][j].im *= rq;
-            }
-        e = plus_diag(t, {1.0, 0.0});
-    }
+        for (int j = 0; j < 3; ++j) {
+            C s = cadd(cmul(ev[1], g.e[i][j]), cmul(ev[2], g2.e[i][j]));
+            if (i == j) s = cadd(s, ev[0]);
+            e.e[i][j] = s;
+        }
     x = mul(up, e);
     return true;
 }
