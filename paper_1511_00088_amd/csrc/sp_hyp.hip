@@ -332,9 +332,142 @@ __device__ __forceinline__ bool proj_series(const M3& w, const M3& up, M3& x) {
     return true;
 }
 
+// Polynomials a0 + a1 E + a2 E^2 in a traceless Hermitian 3x3 matrix E, reduced by its characteristic
+// polynomial E^3 = -e2 E + e3 (e2 = -tr(E^2)/2, e3 = det E).
+template <class T>
+__device__ __forceinline__ void poly_mul(const T (&a)[3], const T (&b)[3], double e2, double e3, T (&r)[3]) {
+    T c[5];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) c[q] = T(0.0);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) c[i + j] = c[i + j] + a[i] * b[j];
+#pragma unroll
+    for (int q = 4; q >= 3; --q) {  // E^q = -e2 E^(q-2) + e3 E^(q-3)
+        c[q - 2] = c[q - 2] - c[q] * e2;
+        c[q - 3] = c[q - 3] + c[q] * e3;
+    }
+#pragma unroll
+    for (int q = 0; q < 3; ++q) r[q] = c[q];
+}
+
+// complex scalar with the operators poly_mul needs
+struct Z {
+    double re, im;
+    __device__ Z() = default;
+    __device__ constexpr Z(double r) : re(r), im(0.0) {}
+    __device__ constexpr Z(double r, double i) : re(r), im(i) {}
+};
+__device__ __forceinline__ Z operator+(Z a, Z b) { return {a.re + b.re, a.im + b.im}; }
+__device__ __forceinline__ Z operator-(Z a, Z b) { return {a.re - b.re, a.im - b.im}; }
+__device__ __forceinline__ Z operator*(Z a, Z b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+__device__ __forceinline__ Z operator*(Z a, double s) { return {a.re * s, a.im * s}; }
+
+// The same maximiser as proj_series, written entirely as a function of S = W^dag W: the polar factor is
+// W S^-1/2 and H^-1 = S^-1/2, so X = W F(S) with F = S^-1/2 exp(i asin(mu S^-1/2)), det W = |det W| e^{i phi}.
+// With s0 = tr S / 3 and E = S / s0 - I (traceless), S^-1/2 = s0^-1/2 sum_k binom(-1/2, k) E^k; all series
+// are carried as coefficients of I, E, E^2, so the matrix products are S, E^2 and W F. Used when
+// |E|_F <= 1/2 (60 terms of the binomial series then leave less than 1e-17) and |mu| |S^-1/2|_F <= 0.06;
+// returns false otherwise.
+__device__ __forceinline__ bool proj_direct(const M3& w, M3& x) {
+    constexpr double c[7] = {1.0, 1.0 / 6, 3.0 / 40, 5.0 / 112, 35.0 / 1152, 63.0 / 2816, 231.0 / 13312};
+    M3 s = mul_dn(w, w);
+    hermitize(s);
+    const double s0 = (s.e[0][0].re + s.e[1][1].re + s.e[2][2].re) * (1.0 / 3.0);
+    if (!(s0 > 0.0) || !isfinite(s0)) return false;
+    const double rs0 = 1.0 / s0;
+    M3 e;
+    double t2 = 0.0;  // tr E^2 = |E|_F^2
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            e.e[i][j] = {s.e[i][j].re * rs0 - (i == j ? 1.0 : 0.0), s.e[i][j].im * rs0};
+            t2 += e.e[i][j].re * e.e[i][j].re + e.e[i][j].im * e.e[i][j].im;
+        }
+    if (!(t2 <= 0.25)) return false;
+    const double e2 = -0.5 * t2, e3 = det3(e).re;
+    // G = S^-1/2
+    double g[3] = {0.0, 0.0, 0.0}, pk[3] = {1.0, 0.0, 0.0}, bk = 1.0;
+#pragma unroll
+    for (int kk = 0; kk < 60; ++kk) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) g[q] += bk * pk[q];
+        const double a0 = pk[0], a1 = pk[1], a2 = pk[2];  // times E
+        pk[0] = a2 * e3;
+        pk[1] = a0 - a2 * e2;
+        pk[2] = a1;
+        bk *= -(2.0 * kk + 1.0) / (2.0 * kk + 2.0);
+    }
+    const double rsq = 1.0 / sqrt(s0);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) g[q] *= rsq;
+    const C dw = det3(w);
+    const double phi = atan2(dw.im, dw.re);
+    double g2[3];
+    poly_mul(g, g, e2, e3, g2);
+    auto trace = [&](const double (&a)[3]) { return 3.0 * a[0] + a[2] * t2; };
+    // odd powers of G and their traces
+    double gp[7][3], p[7];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) gp[0][q] = g[q];
+#pragma unroll
+    for (int n = 1; n < 7; ++n) poly_mul(gp[n - 1], g2, e2, e3, gp[n]);
+#pragma unroll
+    for (int n = 0; n < 7; ++n) p[n] = trace(gp[n]);
+    double mu = -phi / p[0];
+#pragma unroll
+    for (int it = 0; it < 6; ++it) {
+        const double m2 = mu * mu;
+        double f = 0.0, df = 0.0, mp = 1.0;
+#pragma unroll
+        for (int n = 0; n < 7; ++n) {
+            df += c[n] * (2 * n + 1) * p[n] * mp;
+            f += c[n] * p[n] * mp * mu;
+            mp *= m2;
+        }
+        mu -= (f + phi) / df;
+    }
+    if (!(fabs(mu) * sqrt(trace(g2)) <= 0.06)) return false;
+    double th[3] = {0.0, 0.0, 0.0}, mp = mu;
+#pragma unroll
+    for (int n = 0; n < 7; ++n) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) th[q] += c[n] * mp * gp[n][q];
+        mp *= mu * mu;
+    }
+    const Z ith[3] = {Z(0.0, th[0]), Z(0.0, th[1]), Z(0.0, th[2])};
+    Z ev[3] = {Z(1.0), Z(0.0), Z(0.0)};
+#pragma unroll
+    for (int q = 8; q >= 1; --q) {
+        Z t[3];
+        poly_mul(ith, ev, e2, e3, t);
+        const double rq = 1.0 / q;
+        ev[0] = t[0] * rq + Z(1.0);
+        ev[1] = t[1] * rq;
+        ev[2] = t[2] * rq;
+    }
+    const Z gz[3] = {Z(g[0]), Z(g[1]), Z(g[2])};
+    Z f[3];
+    poly_mul(gz, ev, e2, e3, f);
+    const M3 ee = mul(e, e);
+    M3 m;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const C a = cmul({f[1].re, f[1].im}, e.e[i][j]), b = cmul({f[2].re, f[2].im}, ee.e[i][j]);
+            m.e[i][j] = {a.re + b.re + (i == j ? f[0].re : 0.0), a.im + b.im + (i == j ? f[0].im : 0.0)};
+        }
+    x = mul(w, m);
+    return true;
+}
+
 __device__ __forceinline__ M3 proj_su3(const M3& w) {
-    M3 x = polar_factor(w);
     M3 y;
+    if (proj_direct(w, y)) return y;
+    M3 x = polar_factor(w);
     if (proj_series(w, x, y)) return y;
     const C d = det3(x);
     const double th = -atan2(d.im, d.re) / 3.0;
