@@ -197,9 +197,9 @@ size_t sp_hyp_workspace_bytes(const sp_geom* g);
  *                  s = the direction outside {mu, nu, rho}
  *   V_mu         = P[(1 - a1) U_mu + a1/6 sum_{nu != mu} S(lv2(nu, mu); lv2(mu, nu))]
  * with S(A; B)(x) = A_eta(x) B(x+eta) A_eta(x+mu)^dag + A_eta(x-eta)^dag B(x-eta) A_eta(x-eta+mu) for the
- * staple direction eta of the sum, and P(W) = the SU(3) matrix maximising Re tr(X^dag W) (from the
- * unitary polar factor in closed form when its determinant phase is small, else by SU(2)-subgroup sweeps
- * to convergence).
+ * staple direction eta of the sum, and P(W) = the SU(3) matrix maximising Re tr(X^dag W) (in closed
+ * form when W is close enough to unitary up to a factor, else from its unitary polar factor by
+ * SU(2)-subgroup sweeps to convergence).
  * links_nat, out_nat: device, complex128 [4][V][3][3] in the natural layout (lex = x + X(y + Y(z + Z t)));
  * they must not overlap. alpha: host, 3 doubles (a1, a2, a3), each in [0, 1]; (0.75, 0.6, 0.3) is the
  * standard choice. All directions are periodic (bc_t is ignored: it is a fermion boundary condition).

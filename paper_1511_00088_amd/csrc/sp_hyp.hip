@@ -10,12 +10,13 @@
 // with staples of side S around top T in direction eta at x:
 //   S(x) T(x+eta) S(x+mu)^dag + S(x-eta)^dag T(x-eta) S(x-eta+mu).
 //
-// Proj_SU(3)(W) maximises Re tr(X^dag W) over SU(3). First the unitary polar factor of W by scaled Newton
-// iteration X <- (z X + X^-dag / z) / 2, z = |det X|^(-1/3). Where its determinant phase is small enough
-// (the usual case for smeared links) the maximiser then follows in closed form (proj_series below).
-// Otherwise the cube root of the determinant's phase (principal branch) is divided out and sweeps over the
-// three SU(2) subgroups (Cabibbo-Marinari), each taking the subgroup element that maximises the objective,
-// run until a sweep moves no element by more than 1e-15.
+// Proj_SU(3)(W) maximises Re tr(X^dag W) over SU(3). Where W^dag W is close to a multiple of the identity
+// and the determinant phase of W is small (the usual case for smeared links) the maximiser is computed in
+// closed form as a function of W^dag W (proj_direct below). Otherwise the unitary polar factor of W comes
+// from scaled Newton iteration X <- (z X + X^-dag / z) / 2, z = |det X|^(-1/3), and the same closed form
+// is tried from it (proj_series); failing that, the cube root of the determinant's phase (principal
+// branch) is divided out and sweeps over the three SU(2) subgroups (Cabibbo-Marinari), each taking the
+// subgroup element that maximises the objective, run until a sweep moves no element by more than 1e-15.
 //
 // One thread per (site, field); blockIdx.y selects the field, so a wavefront covers 64 consecutive sites
 // of one field. Every level is FP64. Input and output links use the natural layout [4][V][3][3] complex128

@@ -4,8 +4,8 @@ Small lattices are compared link by link with the oracle's full result; the 20^3
 sampled links against the committed oracle values (tests/golden/hyp_cfg1_samples.txt), plus properties
 that hold at any size (every output link in SU(3), determinism). Both sides compute the maximiser of
 Re tr(X^dag W) over SU(3): the oracle by SU(2)-subgroup sweeps from the SVD polar factor, the GPU in closed
-form from its Newton polar factor where the determinant phase is small (sweeps elsewhere, e.g. on most
-matrices of a Haar field); they agree to rounding, and the tests ask for 1e-12.
+form where that applies (every matrix of the workload field) and by sweeps from a Newton polar factor
+elsewhere (most matrices of a Haar field); they agree to rounding, and the tests ask for 1e-12.
 """
 import os
 
