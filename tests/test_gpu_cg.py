@@ -189,8 +189,15 @@ def test_control_lattice_true_residual_through_the_operator(inner, recon):
     dims = (32, 32, 32, 64)
     announce(f"control lattice {dims} {inner} r{recon}")
     lat = sp.Lattice(dims)
+    links, b = _gpu_links_and_source(lat, 71)
+    _solve_and_check_operator_residual(lat, links, b, inner, recon)
+
+
+def _gpu_links_and_source(lat, seed):
+    """Near-identity links exp(i 0.3 H) and a Gaussian even source drawn on the GPU (seeded torch generator):
+    these lattices are too large for the host generator to be quick."""
     gen = torch.Generator(device="cuda:0")
-    gen.manual_seed(71)
+    gen.manual_seed(seed)
     V = lat.V
     lam = torch.from_numpy((li.gell_mann() / 2.0).reshape(8, 9)).to("cuda:0")
     links = torch.empty(4, V, 3, 3, dtype=torch.complex128, device="cuda:0")
@@ -198,8 +205,11 @@ def test_control_lattice_true_residual_through_the_operator(inner, recon):
         h = torch.randn(V, 8, generator=gen, device="cuda:0", dtype=torch.float64).to(torch.complex128)
         links[mu] = torch.linalg.matrix_exp((0.3j) * (h @ lam).reshape(V, 3, 3))
     b = torch.randn(lat.Vh, 3, dtype=torch.complex128, device="cuda:0", generator=gen)
+    return links, b
+
+
+def _solve_and_check_operator_residual(lat, links, b, inner, recon, m=0.01):
     G = sp.Gauge(lat, links, lo_prec=inner, recon=recon)
-    m = 0.01
     x, st = sp.cg_solve(G, m, b, tol=1e-8, inner=inner)
     assert st.converged, st
     t = sp.dslash(G, x, 1, "f64")       # D_oe x
@@ -207,6 +217,28 @@ def test_control_lattice_true_residual_through_the_operator(inner, recon):
     res = (torch.linalg.norm(b - Ax) / torch.linalg.norm(b)).item()
     announce(f"  iters={st.iters} ru={st.reliable_updates} solver resid={st.true_rel_resid:.3e} operator resid={res:.3e}")
     assert res <= 1.01e-8 and abs(res - st.true_rel_resid) <= 1e-3 * res
+    return G
+
+
+def test_production_lattice_28x28x28x96():
+    """The paper's other production lattice (28^3x96, Sec. 4): the FP32 recon-12 half operator at sampled sites
+    against the oracle, then a mixed solve whose true residual is recomputed with the FP64 operator."""
+    dims = (28, 28, 28, 96)
+    announce(f"production lattice {dims}")
+    lat = sp.Lattice(dims)
+    links, b = _gpu_links_and_source(lat, 72)
+    G = _solve_and_check_operator_residual(lat, links, b, "f32", 12)
+    U = to_host(links)
+    xin = li.gaussian_vector(lat.Vh, 106)
+    rng = np.random.default_rng(107)
+    cbs = np.unique(np.concatenate([rng.integers(0, lat.Vh, 2000), np.arange(lat.Vh - 200, lat.Vh),
+                                    np.arange(0, 200)]))
+    for p in (0, 1):
+        y = to_host(sp.dslash(G, to_dev(xin), p, "f32"))[cbs]
+        ref = oracle.dslash_eo_sites(dims, U, xin, p, cbs)
+        err = float(np.max(np.abs(y - ref)) / np.max(np.abs(ref)))
+        announce(f"  parity {p}: sampled max rel err {err:.3e}")
+        assert err <= 1e-6
 
 
 @pytest.mark.parametrize("inner,recon", [("f32", 12), ("f64", 18), ("f16", 12)])
