@@ -477,7 +477,7 @@ __device__ __forceinline__ M3 proj_su3(const M3& w) {
     for (int i = 0; i < 3; ++i)
 #pragma unroll
         for (int j = 0; j < 3; ++j) x.e[i][j] = cmul(x.e[i][j], ph);
-    for (int sweep = 0; sweep < 200; ++sweep) {
+    for (int sweep = 0; sweep < 500; ++sweep) {  // nearly singular W can need hundreds
         const M3 x0 = x;
         su2_step(x, w, 0, 1);
         su2_step(x, w, 0, 2);

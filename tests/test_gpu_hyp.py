@@ -36,6 +36,8 @@ def _gpu_hyp(dims, U, alpha=hyp.HYP_ALPHA):
     ((6, 4, 4, 6), "near", (0.5, 0.3, 0.9)),
     ((4, 4, 4, 4), "haar", hyp.HYP_ALPHA),
     ((8, 8, 8, 8), "near", hyp.HYP_ALPHA),
+    ((4, 4, 4, 4), "near", (1.0, 1.0, 1.0)),
+    ((4, 4, 4, 4), "haar", (1.0, 0.0, 1.0)),
 ])
 def test_hyp_matches_oracle(dims, kind, alpha):
     announce(f"hyp dims={dims} {kind} alpha={alpha}")
@@ -43,6 +45,23 @@ def test_hyp_matches_oracle(dims, kind, alpha):
     V = _gpu_hyp(dims, U, alpha)
     ref = hyp.hyp_smear(dims, U, alpha)
     assert np.max(np.abs(V - ref)) <= 1e-12
+
+
+def test_largest_weights_on_haar_links_ill_conditioned_maximum():
+    # weights (1, 1, 1) on Haar links give staple sums whose determinant phase sits at +-pi; there the
+    # maximiser of Re tr(X^dag W) lies along a nearly flat direction and the SU(2)-subgroup sweeps converge
+    # with a rate near 1 (the oracle needs up to its 500-sweep cap): the maximum itself is fixed to rounding,
+    # the maximising link only to about 1e-6
+    dims = (4, 4, 4, 4)
+    announce("hyp weights (1, 1, 1) on Haar links")
+    U = li.haar_links(dims, 461)
+    alpha = (1.0, 1.0, 1.0)
+    V = _gpu_hyp(dims, U, alpha)
+    ref = hyp.hyp_smear(dims, U, alpha)
+    eye = np.eye(3)
+    assert np.max(np.abs(V @ np.conj(np.swapaxes(V, -1, -2)) - eye)) <= 1e-13
+    assert np.max(np.abs(np.linalg.det(V) - 1.0)) <= 1e-13
+    assert np.max(np.abs(V - ref)) <= 1e-5
 
 
 def test_zero_weights_give_the_links_back():
