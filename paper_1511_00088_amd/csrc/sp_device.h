@@ -217,16 +217,19 @@ struct VecFmt16 {
     __device__ static void store(void* base, int Vh, int cb, const Vec3<float>& v) { (void)store_rt(base, Vh, cb, v); }
     // store and return the value as stored (rounded to 16 bits, scaled by the site norm)
     __device__ static Vec3<float> store_rt(void* base, int Vh, int cb, const Vec3<float>& v) {
-        float inv = 1.0f, m = 1.0f;
+        float inv = 1.0f, m = 1.0f, k = 1.0f;
         if constexpr (scaled) {
             m = 0.0f;
 #pragma unroll
             for (int c = 0; c < 3; ++c) m = fmaxf(m, fmaxf(fabsf(v.c[c].re), fabsf(v.c[c].im)));
-            inv = m > 0.0f ? 1.0f / m : 0.0f;
+            // a site norm near the bottom of the FP32 range (the last residuals of a source of norm ~1e-30)
+            // would overflow 1/m: scale the site by 2^64 (exact) before dividing
+            k = m < 1.0e-30f ? 18446744073709551616.0f : 1.0f;
+            inv = m > 0.0f ? 1.0f / (m * k) : 0.0f;
         }
-        const uint32_t w0 = pack2<P>(inv * v.c[0].re, inv * v.c[0].im);
-        const uint32_t w1 = pack2<P>(inv * v.c[1].re, inv * v.c[1].im);
-        const uint32_t w2 = pack2<P>(inv * v.c[2].re, inv * v.c[2].im);
+        const uint32_t w0 = pack2<P>(inv * (k * v.c[0].re), inv * (k * v.c[0].im));
+        const uint32_t w1 = pack2<P>(inv * (k * v.c[1].re), inv * (k * v.c[1].im));
+        const uint32_t w2 = pack2<P>(inv * (k * v.c[2].re), inv * (k * v.c[2].im));
         if constexpr (scaled) {
             ((uint4*)base)[cb] = make_uint4(w0, w1, w2, __float_as_uint(m));
         } else {

@@ -271,3 +271,23 @@ def test_schedules_reach_the_same_solution(inner, recon):
         # the same reliable-update positions (delta and ru_every checked at chunk ends of length 1 vs 25 differ,
         # so compare the recurrence-free schedule with the default one loosely)
         assert iters[(25, 0, 0.1)] <= 1.05 * iters[(1, 0, 0.1)] + 2
+
+
+@pytest.mark.parametrize("inner,recon", [("f64", 18), ("f32", 12), ("f16", 12), ("bf16", 12)])
+def test_solution_scales_with_the_source(inner, recon):
+    # A x = b is linear: sources scaled by 1e-30 and 1e30 must give the scaled solution. At 1e-30 the last
+    # residuals reach the bottom of the FP32 range (~1e-38), where the FP16 site norm must not overflow
+    # its reciprocal
+    dims = (8, 8, 8, 8)
+    U = li.near_identity_links(dims, 0.3, 211)
+    b = to_dev(li.gaussian_even_source(dims, 212))
+    G = gauge(dims, U, inner, recon)
+    x1, st1 = sp.cg_solve(G, 0.02, b, tol=1e-8, inner=inner)
+    assert st1.converged
+    for s in (1e-30, 1e30):
+        announce(f"cg {inner} r{recon} source scale {s:g}")
+        xs, st = sp.cg_solve(G, 0.02, b * s, tol=1e-8, inner=inner, raise_on_not_converged=True)
+        diff = (torch.linalg.norm(xs / s - x1) / torch.linalg.norm(x1)).item()
+        announce(f"  iters={st.iters} (unscaled {st1.iters}) resid={st.true_rel_resid:.2e} diff={diff:.2e}")
+        assert st.converged and st.true_rel_resid <= 1e-8
+        assert diff <= 1e-6
