@@ -487,6 +487,7 @@ SolverState initial_state(const sp_system& s, const sp_cg_params* prm) {
     st.tol2 = prm->tol * prm->tol;
     // plain FP64 CG recomputes the true residual only when the iterated one says it has converged
     st.delta2 = (prm->delta > 0 && prm->inner != SP_F64) ? prm->delta * prm->delta : 0.0;
+    st.floor2 = prm->inner != SP_F64 ? 1e-6 : 0.0;  // |r| three decades below the last true residual
     st.m2 = s.mass * s.mass;
     st.max_iter = prm->max_iter;
     int every = prm->ru_every;

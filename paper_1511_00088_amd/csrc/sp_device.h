@@ -529,6 +529,7 @@ struct alignas(64) SolverState {
     double stop2;     // tol^2 |b|^2
     double tol2;      // tol^2
     double delta2;    // delta^2
+    double floor2;    // any-iteration trigger: |r|^2 below floor2 * rr_ru (0: off)
     double true_rho;  // last true |r|^2
     double best_rho;  // best true |r|^2 so far (stagnation)
     double m2;        // mass^2
@@ -549,8 +550,9 @@ __device__ __forceinline__ void fin_alpha(SolverState* st, double pq) {
 }
 
 // After r -= alpha q. A reliable update is requested (the iteration's p update is then left to it) on
-// apparent convergence and at the iteration cap at any iteration; on the last iteration of a chunk also
-// when |r| fell below delta |r_true at the last update| or ru_every iterations have passed. Keeping the
+// apparent convergence, at the iteration cap and when |r| fell three decades below |r_true at the last
+// update| at any iteration; on the last iteration of a chunk also when |r| fell below delta |r_true at the
+// last update| or ru_every iterations have passed. Keeping the
 // last two triggers at chunk ends means a chunk never stops early for them.
 __device__ __forceinline__ void fin_update(SolverState* st, double rho_new, bool chunk_end) {
     st->iter += 1;
@@ -560,6 +562,10 @@ __device__ __forceinline__ void fin_update(SolverState* st, double rho_new, bool
         return;
     }
     bool pause = rho_new <= st->stop2 || st->iter >= st->max_iter;
+    // the recursive residual has fallen three decades below the last true one: further than a low-precision
+    // recursion stays accurate; left until the chunk end, it can run many decades below the true residual
+    // in a fast-converging solve, and the update would then restart from a direction scaled by their ratio
+    pause |= rho_new < st->floor2 * st->rr_ru;
     if (chunk_end) {
         pause |= st->delta2 > 0.0 && rho_new < st->delta2 * st->rr_ru;
         pause |= st->iter - st->iter_last_ru >= st->ru_every;
