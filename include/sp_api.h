@@ -84,7 +84,9 @@ typedef struct {
  *             (<= 0 picks 25)
  *  use_x0     1: x_e holds the initial guess on entry; 0: start from zero
  *  use_graph  1: capture each chunk in a hipGraph and replay it; 0: launch kernels one by one
- * A reliable update also runs whenever the iterated residual reaches tol and at the iteration cap. After
+ * A reliable update also runs whenever the iterated residual reaches tol, at the iteration cap, and (for
+ * SP_F32, SP_F16, SP_BF16) when the iterated residual falls three decades below the true residual of the
+ * last update. After
  * it, FP32 iterations keep the search direction (re-orthogonalised against the new residual); 16-bit
  * storage restarts it from the residual. */
 typedef struct {
