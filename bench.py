@@ -222,7 +222,7 @@ def bench_hyp(sp, torch, lat, links, stream, log):
     log(f"HYP smearing {lat.dims}: {t * 1e3:.2f} ms ({gbs:.0f} GB/s of algorithmic bytes)")
     return {"dims": list(lat.dims), "ms": t * 1e3, "alpha": list(sp.HYP_ALPHA),
             "bytes_per_site": HYP_BYTES_PER_SITE, "achieved_GBs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS,
-            "note": "three FP64 levels with SU(3) projections (Newton polar factor, then the closed-form maximiser or SU(2)-subgroup sweeps); "
+            "note": "three FP64 levels with SU(3) projections (the closed-form maximiser, else a Newton polar factor and series, else SU(2)-subgroup sweeps); "
                     "bound by FP64 arithmetic, not bytes"}
 
 
