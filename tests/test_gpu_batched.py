@@ -78,6 +78,70 @@ def test_batched_masses_two_decades_apart(inner, recon):
         assert err <= 1e-6
 
 
+@pytest.mark.parametrize("inner,recon", [("f32", 12), ("f16", 18), ("bf16", 12), ("f64", 18)])
+def test_batched_antiperiodic_groups_beside_periodic(inner, recon):
+    """Groups whose time boundary differs in the same launches: one link field on 6x8x4x12 packed with
+    antiperiodic and with periodic time, and an antiperiodic 4^4 field. Every system against the oracle's
+    solution with its own boundary condition, and its true residual recomputed by the oracle."""
+    announce(f"batched antiperiodic and periodic groups {inner} r{recon}")
+    specs = [((6, 8, 4, 12), 1, 350, [0.03, 0.08]), ((6, 8, 4, 12), 0, 350, [0.05]), ((4, 4, 4, 4), 1, 351, [0.1, 0.02])]
+    systems, host = [], []
+    k = 0
+    for dims, bc, seed, masses in specs:
+        U = li.near_identity_links(dims, 0.3, seed)
+        G = gauge(dims, U, inner, recon, bc)
+        for m in masses:
+            b = li.gaussian_even_source(dims, 360 + k)
+            k += 1
+            systems.append((G, m, to_dev(b)))
+            host.append((dims, bc, U, m, b))
+    xs, stats = sp.cg_solve_batched(systems, tol=1e-8, inner=inner)
+    for (dims, bc, U, m, b), x, st in zip(host, xs, stats):
+        xr, _, it0, _ = oracle.cg_solve(dims, U, m, b, tol=1e-12, bc_t=bc)
+        xh = to_host(x)
+        err = rel_err_2(xh, xr)
+        res = float(np.linalg.norm(b - oracle.apply_A(dims, U, m, xh, bc_t=bc)) / np.linalg.norm(b))
+        announce(f"  dims={dims} bc_t={bc} m={m}: iters={st.iters} (oracle {it0}) resid={res:.2e} err={err:.2e}")
+        assert st.converged and res <= 1.5e-8
+        assert err <= 1e-6
+
+
+def test_batched_zero_source_beside_others():
+    """A zero right-hand side in a group with two others: it stops at the initial residual check with x = 0,
+    while the group's other systems run on to the oracle's solution."""
+    dims = (8, 4, 4, 8)
+    U = li.near_identity_links(dims, 0.3, 370)
+    G = gauge(dims, U, "f32", 12)
+    b1 = li.gaussian_even_source(dims, 371)
+    b3 = li.gaussian_even_source(dims, 372)
+    zero = np.zeros_like(b1)
+    xs, stats = sp.cg_solve_batched([(G, 0.05, to_dev(b1)), (G, 0.05, to_dev(zero)), (G, 0.02, to_dev(b3))],
+                                    tol=1e-9, inner="f32")
+    assert stats[1].converged and stats[1].iters == 0 and float(xs[1].abs().max()) == 0.0
+    for i, (m, b) in ((0, (0.05, b1)), (2, (0.02, b3))):
+        xr, _, _, _ = oracle.cg_solve(dims, U, m, b, tol=1e-12)
+        assert stats[i].converged and stats[i].iters > 0
+        assert rel_err_2(to_host(xs[i]), xr) <= 1e-7
+
+
+def test_batched_iteration_cap():
+    """max_iter cuts every system of a batch at the same count: each reports not converged (status 1) after
+    exactly max_iter iterations, and its reported true residual is that of the x it returns, recomputed by
+    the oracle."""
+    dims = (4, 4, 4, 8)
+    U = li.near_identity_links(dims, 0.3, 380)
+    G = gauge(dims, U, "f32", 12)
+    bs = [li.gaussian_even_source(dims, 381 + i) for i in range(3)]
+    masses = [0.01, 0.02, 0.05]
+    xs, stats = sp.cg_solve_batched([(G, m, to_dev(b)) for m, b in zip(masses, bs)], tol=1e-10, inner="f32",
+                                    max_iter=7)
+    for m, b, x, st in zip(masses, bs, xs, stats):
+        res = float(np.linalg.norm(b - oracle.apply_A(dims, U, m, to_host(x))) / np.linalg.norm(b))
+        assert st.status == 1 and not st.converged and st.iters == 7
+        assert 1e-10 < res < 1.0
+        assert abs(res - st.true_rel_resid) <= 1e-6 * res
+
+
 def test_batched_deterministic():
     systems, _ = _batch("f32")
     xa, sa = sp.cg_solve_batched(systems, tol=1e-8, inner="f32")
