@@ -8,6 +8,7 @@ links packed and source resident in HBM before the timed region. Beside it, in t
   * the plain FP64 GPU CG to the same residual (the comparator),
   * the half-Dslash kernel timed with HIP events on the stream it runs on (roofline),
   * the FP64 CPU oracle timed on a bounded sample (FP64 CG iterations on the same lattice).
+  * the packing of links and vectors, done once per gauge field or source and reported apart.
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -296,6 +297,40 @@ def bench_gradient(sp, li, torch, dev, log):
     return {"dims": list(c["dims"]), "s": t, "note": "forward solve + adjoint solve to 1e-10 + force kernels"}
 
 
+def bench_packing(sp, torch, lat, links, b, inner, recon, stream, log):
+    """Packing, done once per gauge field (links) or per source and solution (vectors) and not part of the
+    time-to-solution: natural complex128 links to the FP64 recon-18 layout and to the inner precision's
+    layout, a source to the packed layout and back. HIP events over back-to-back calls on the stream they
+    run on; bytes are what one call reads plus what it writes."""
+    nat_links = 4 * lat.V * 9 * 16
+    nat_vec = lat.Vh * 3 * 16
+    packed = sp.pack_vec(lat, b, inner)
+    cases = [("links_f64_r18", lambda: sp.pack_gauge(lat, links, "f64", 18), nat_links + lat.gauge_bytes("f64", 18)),
+             (f"links_{inner}_r{recon}", lambda: sp.pack_gauge(lat, links, inner, recon),
+              nat_links + lat.gauge_bytes(inner, recon)),
+             (f"vec_pack_{inner}", lambda: sp.pack_vec(lat, b, inner), nat_vec + lat.vec_bytes(inner)),
+             (f"vec_unpack_{inner}", lambda: sp.unpack_vec(lat, packed, inner), lat.vec_bytes(inner) + nat_vec)]
+    out = {}
+    for name, fn, nbytes in cases:
+        fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        n = 10
+        e0.record(stream)
+        for _ in range(n):
+            fn()
+        e1.record(stream)
+        e1.synchronize()
+        t = e0.elapsed_time(e1) / 1e3 / n
+        out[name] = {"us": t * 1e6, "bytes": nbytes, "hbm_frac": nbytes / t / 1e9 / HBM_PEAK_GBS}
+    log("packing: " + ", ".join(f"{k} {v['us']:.1f} us" for k, v in out.items()))
+    out["note"] = ("natural complex128 input already in HBM; the recon-12 packing reads whole links (the dropped "
+                   "row shares their cache lines); the vector calls are short enough that the rate of the Python "
+                   "calls, not the kernel, sets their time")
+    return out
+
+
 def cpu_model():
     try:
         with open("/proc/cpuinfo") as f:
@@ -522,6 +557,7 @@ def main():
         extra["npr"] = bench_npr(sp, torch, lat, G64_links(), stream, log)
         extra["batched"] = bench_batched(sp, li, torch, dev, log)
         extra["gradient"] = bench_gradient(sp, li, torch, dev, log)
+        extra["packing"] = bench_packing(sp, torch, lat, G64_links(), b, args.inner, args.recon, stream, log)
 
     cpu = None
     if not args.no_cpu:
