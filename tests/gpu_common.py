@@ -1,4 +1,6 @@
 """Shared helpers of the GPU parity tests (device transfer, tolerances)."""
+import os
+
 import numpy as np
 import torch
 
@@ -27,3 +29,17 @@ def gauge(dims, links: np.ndarray, prec="f32", recon=18, bc_t=0):
 
 def announce(msg: str):
     print(msg, flush=True)
+
+
+def cfg1_golden():
+    """Site indices and values of the 20^3x64 workload's solution sampled from the oracle's 1e-12 solve
+    (written by tests/golden/make_cfg1_samples.py, which calls only the oracle)."""
+    path = os.path.join(os.path.dirname(__file__), "golden", "cfg1_solution_samples.txt")
+    rows = np.loadtxt(path)
+    cbs = rows[:, 0].astype(np.int64)
+    vals = rows[:, 1::2] + 1j * rows[:, 2::2]
+    return cbs, vals
+
+
+def tune_file():
+    return os.path.join(os.path.dirname(os.path.dirname(__file__)), "paper_1511_00088_amd", "tune_mi355x.json")

@@ -3,12 +3,13 @@ different volumes advance in the same launches, converged systems stop while the
 Every system is compared with the oracle's solution and with the same system solved alone."""
 import numpy as np
 import pytest
+import torch
 
 import lattice_inputs as li
 import oracle
 import paper_1511_00088_amd as sp
 from conftest import rel_err_2
-from gpu_common import announce, gauge, to_dev, to_host
+from gpu_common import announce, cfg1_golden, gauge, to_dev, to_host, tune_file
 
 pytestmark = pytest.mark.gpu
 
@@ -140,6 +141,36 @@ def test_batched_iteration_cap():
         assert st.status == 1 and not st.converged and st.iters == 7
         assert 1e-10 < res < 1.0
         assert abs(res - st.true_rel_resid) <= 1e-6 * res
+
+
+def test_batched_full_size_workload_vs_oracle_samples():
+    """The 20^3x64 workload inside a batch, in the launch configuration the benchmark times (FP32 iterations on
+    recon-12 links, the tuned four-right-hand-side operator): the workload's own system (m = 0.01) and three
+    more sources and masses on its field form one group, and four systems on a 16^3x32 field run in the same
+    launches. The workload's solution at the sampled sites against the oracle's 1e-12 solution (golden file
+    written by the oracle alone); every system's true residual recomputed with the FP64 half operator entry
+    point, independently of the solver's reliable updates."""
+    sp.tune_load(tune_file())
+    c = li.cfg1()
+    c4 = li.cfg4()
+    G1 = gauge(c["dims"], c["links"], "f32", 12)
+    G4 = gauge(c4["dims"], c4["links"], "f32", 12)
+    systems = [(G1, c["mass"], to_dev(c["source"]))]
+    systems += [(G1, m, to_dev(li.gaussian_even_source(c["dims"], 390 + i))) for i, m in enumerate([0.02, 0.05, 0.1])]
+    systems += [(G4, m, to_dev(li.gaussian_even_source(c4["dims"], 395 + i))) for i, m in enumerate([0.01, 0.03, 0.05, 0.08])]
+    announce("batched full size: 4 systems on 20^3x64 + 4 on 16^3x32, f32 r12")
+    xs, stats = sp.cg_solve_batched(systems, tol=1e-8, inner="f32")
+    for (G, m, b), x, st in zip(systems, xs, stats):
+        t = sp.dslash(G, x, 1, "f64")
+        ax = m * m * x - sp.dslash(G, t, 0, "f64")
+        res = (torch.linalg.norm(b - ax) / torch.linalg.norm(b)).item()
+        announce(f"  {G.lat.dims} m={m}: iters={st.iters} ru={st.reliable_updates} solver resid={st.true_rel_resid:.3e} "
+                 f"operator resid={res:.3e}")
+        assert st.converged and res <= 1.01e-8 and abs(res - st.true_rel_resid) <= 1e-3 * res
+    cbs, ref = cfg1_golden()
+    err = np.linalg.norm(to_host(xs[0])[cbs] - ref) / np.linalg.norm(ref)
+    announce(f"  workload system: sampled err vs oracle {err:.3e}")
+    assert err <= 1e-6
 
 
 def test_batched_deterministic():

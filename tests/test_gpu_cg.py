@@ -12,7 +12,7 @@ import lattice_inputs as li
 import oracle
 import paper_1511_00088_amd as sp
 from conftest import rel_err_2
-from gpu_common import announce, gauge, to_dev, to_host
+from gpu_common import announce, cfg1_golden, gauge, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
@@ -115,16 +115,6 @@ def _cfg1():
     return _CFG1
 
 
-def _cfg1_golden():
-    import os
-
-    path = os.path.join(os.path.dirname(__file__), "golden", "cfg1_solution_samples.txt")
-    rows = np.loadtxt(path)
-    cbs = rows[:, 0].astype(np.int64)
-    vals = rows[:, 1::2] + 1j * rows[:, 2::2]
-    return cbs, vals
-
-
 @pytest.mark.parametrize("inner,recon", [("f32", 18), ("f64", 18), ("f32", 12), ("f16", 18), ("bf16", 18),
                                          ("f16", 12), ("bf16", 12)])
 def test_cfg1_full_size_vs_oracle_samples(inner, recon):
@@ -141,7 +131,7 @@ def test_cfg1_full_size_vs_oracle_samples(inner, recon):
     G = gauge(dims, U, inner, recon)
     x, st = sp.cg_solve(G, m, to_dev(b), tol=1e-8, inner=inner)
     x = to_host(x)
-    cbs, ref = _cfg1_golden()
+    cbs, ref = cfg1_golden()
     err = np.linalg.norm(x[cbs] - ref) / np.linalg.norm(ref)
     res = _true_resid(dims, U, m, b, x)
     announce(f"  iters={st.iters} ru={st.reliable_updates} resid={st.true_rel_resid:.3e} oracle-resid={res:.3e} "
