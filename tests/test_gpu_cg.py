@@ -163,6 +163,38 @@ def test_full_system_solve(dims, bc_t, inner, links):
     assert res <= 1e-9
 
 
+def test_full_system_solve_workload_size():
+    """(m + D) psi = src on 20^3x64 (m = 0.01) with the benchmark's FP32 recon-12 launch, checked through the FP64
+    half operator entry point: the odd half satisfies its rows to rounding (psi_o = (src_o - D_oe psi_e) / m),
+    and the even rows' residual is the even solve's, (b_e - A psi_e) / m with b_e = m src_e - D_eo src_o, so
+    its norm is the reported relative residual times |b_e| / m and at most tol |b_e| / m."""
+    c = _cfg1()
+    dims, m = c["dims"], c["mass"]
+    lat = sp.Lattice(dims)
+    G = sp.Gauge(lat, to_dev(c["links"]), lo_prec="f32", recon=12)
+    src = li.gaussian_vector(lat.V, 510)
+    announce(f"full solve at the workload size {dims}")
+    psi, st = sp.full_solve(G, m, to_dev(src), tol=1e-8, inner="f32")
+    X, Y, Z, _ = dims
+    lex = np.arange(lat.V)
+    par = (lex % X + (lex // X) % Y + (lex // (X * Y)) % Z + lex // (X * Y * Z)) & 1
+    idx = [np.empty(lat.Vh, dtype=np.int64) for _ in range(2)]
+    for q in (0, 1):
+        idx[q][lex[par == q] >> 1] = lex[par == q]
+    ph = to_host(psi)
+    se, so, pe, po = (to_dev(a) for a in (src[idx[0]], src[idx[1]], ph[idx[0]], ph[idx[1]]))
+    r_o = so - m * po - sp.dslash(G, pe, 1, "f64")
+    r_e = se - m * pe - sp.dslash(G, po, 0, "f64")
+    b_e = m * se - sp.dslash(G, so, 0, "f64")
+    nb = torch.linalg.norm(b_e).item()
+    ro = (torch.linalg.norm(r_o) / torch.linalg.norm(so)).item()
+    re = torch.linalg.norm(r_e).item() * m / nb
+    announce(f"  iters={st.iters} even residual {re:.3e} (reported {st.true_rel_resid:.3e}), odd rows {ro:.1e}")
+    assert st.converged
+    assert ro <= 1e-12
+    assert re <= 1.01e-8 and abs(re - st.true_rel_resid) <= 1e-3 * re
+
+
 def test_full_system_solve_rejects_zero_mass():
     dims = (4, 4, 4, 4)
     G = gauge(dims, li.haar_links(dims, 503), "f32")
