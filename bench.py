@@ -138,6 +138,8 @@ def copy_bandwidth(torch, dev, stream, n=1 << 30, reps=10):
 
 KERNEL_SOURCES = ["paper_1511_00088_amd/csrc/sp_device.h", "paper_1511_00088_amd/csrc/sp_kernels.h",
                   "paper_1511_00088_amd/csrc/sp_launch_dslash.hip", "paper_1511_00088_amd/tune_mi355x.json"]
+
+
 def traffic_file(prec, recon, dims):
     return os.path.join(ROOT, "profiles", f"dslash_{prec}_r{recon}_{dims[0]}x{dims[1]}x{dims[2]}x{dims[3]}_traffic.md")
 

@@ -163,7 +163,8 @@ int sp_cg_solve(const sp_geom* g, const sp_gauge* U, double mass, const double* 
 
 /* Solve nsys independent systems together: systems sharing a gauge field and geometry form groups of up
  * to 4 right-hand sides; all groups advance in one launch per kernel, captured in a hipGraph per chunk
- * of iterations; converged systems stop updating while the others continue. stats: host array of nsys
+ * of iterations; converged systems stop updating while the others continue. Groups may differ in volume
+ * and time boundary; a zero b_e stops at the first residual check with x_e = 0. stats: host array of nsys
  * (nullable). Returns SP_OK if every system converged, SP_NOT_CONVERGED if any did not, or an error.
  * Synchronous with respect to stream. */
 int sp_cg_solve_batched(int nsys, const sp_system* systems, const sp_cg_params* params,
