@@ -27,6 +27,9 @@
  *    code, sp_last_error() gives the detailed message of the calling thread's last failure (including
  *    the HIP error string for SP_ERR_HIP). No C++ exception crosses this interface.
  *  - Not reentrant on one workspace: two calls that share a workspace must not overlap.
+ *  - Host threads: the solves (sp_cg_solve, sp_cg_solve_batched and the even solve inside sp_full_solve)
+ *    hold one library-wide lock from entry to return, so solves issued from several host threads run
+ *    one after another; sp_dslash takes the lock only to read the tuning table.
  */
 #ifndef SP_API_H
 #define SP_API_H
