@@ -106,6 +106,44 @@ def test_zero_source():
     assert st.converged and st.iters == 0 and float(x.abs().max()) == 0.0
 
 
+def test_solves_from_two_host_threads_match_sequential():
+    """Two host threads, each with its own torch stream and workspace, solve different systems three times
+    at once (ctypes releases the interpreter lock, so the calls overlap on the host). The library serialises
+    the solves, and every result equals the same solve run alone, bit for bit."""
+    import threading
+
+    dims = (8, 8, 8, 8)
+    U = li.near_identity_links(dims, 0.3, 410)
+    G = gauge(dims, U, "f32", 12)
+    bs = [to_dev(li.gaussian_even_source(dims, 411 + i)) for i in range(2)]
+    ms = [0.02, 0.05]
+    ref = [sp.cg_solve(G, m, b, tol=1e-9, inner="f32")[0] for m, b in zip(ms, bs)]
+    torch.cuda.synchronize()
+    out, err = [[], []], []
+
+    def run(i):
+        try:
+            s = torch.cuda.Stream()
+            with torch.cuda.stream(s):
+                ws = sp.Workspace()
+                for _ in range(3):
+                    out[i].append(sp.cg_solve(G, ms[i], bs[i], tol=1e-9, inner="f32", workspace=ws))
+            s.synchronize()
+        except Exception as e:  # reported below, in the main thread
+            err.append(e)
+
+    th = [threading.Thread(target=run, args=(i,)) for i in range(2)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join(timeout=120)
+    assert not err and not any(t.is_alive() for t in th), err
+    for i in range(2):
+        assert len(out[i]) == 3
+        for x, st in out[i]:
+            assert st.converged and bool((x == ref[i]).all())
+
+
 _CFG1 = {}
 
 
