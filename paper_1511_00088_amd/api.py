@@ -37,6 +37,18 @@ def _check_c128(t: torch.Tensor, shape, name):
         raise ValueError(f"{name} must be contiguous")
 
 
+def _check_packed(t: torch.Tensor, nbytes: int, name, device=None):
+    """A packed buffer goes to the library as a bare pointer: check here what the kernels will read or write."""
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.uint8 or not t.is_cuda:
+        raise TypeError(f"{name} must be a uint8 GPU tensor (a packed buffer)")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() < nbytes:
+        raise ValueError(f"{name} holds {t.numel()} bytes, the packed layout needs {nbytes}")
+    if device is not None and t.device != device:
+        raise ValueError(f"{name} is on {t.device}, the gauge field on {device}")
+
+
 class Lattice:
     """Lattice extents (X, Y, Z, T), each even, and the time boundary (0 periodic, 1 antiperiodic)."""
 
@@ -88,6 +100,7 @@ def pack_vec(lat: Lattice, v: torch.Tensor, prec) -> torch.Tensor:
 
 
 def unpack_vec(lat: Lattice, packed: torch.Tensor, prec) -> torch.Tensor:
+    _check_packed(packed, lat.vec_bytes(prec), "packed vector")
     out = torch.empty((lat.Vh, 3), dtype=torch.complex128, device=packed.device)
     L.check(L.load().sp_vec_unpack(ctypes.byref(lat.geom), _ptr(packed), _prec(prec), _ptr(out), _stream()),
             "sp_vec_unpack")
@@ -97,8 +110,11 @@ def unpack_vec(lat: Lattice, packed: torch.Tensor, prec) -> torch.Tensor:
 def dslash_packed(gauge: Gauge, prec, inp: torch.Tensor, out_parity: int, out: torch.Tensor | None = None):
     """out (parity out_parity) = D_{p,1-p} inp on packed vectors of precision prec."""
     lat = gauge.lat
+    nbytes = lat.vec_bytes(prec)
+    _check_packed(inp, nbytes, "inp", gauge.f64.device)
     if out is None:
-        out = torch.empty(lat.vec_bytes(prec), dtype=torch.uint8, device=inp.device)
+        out = torch.empty(nbytes, dtype=torch.uint8, device=inp.device)
+    _check_packed(out, nbytes, "out", gauge.f64.device)
     L.check(L.load().sp_dslash(ctypes.byref(lat.geom), ctypes.byref(gauge.struct), _prec(prec), _ptr(inp),
                                _ptr(out), int(out_parity), _stream()), "sp_dslash")
     return out

@@ -155,3 +155,14 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "nope.so"))
     with pytest.raises(RuntimeError, match="missing"):
         _lib.load()
+
+
+def test_packed_buffers_checked_before_any_call():
+    # a packed buffer reaches the library as a bare pointer, so the binding refuses what is not one
+    import torch
+
+    lat = sp.Lattice((4, 4, 4, 4))
+    with pytest.raises(TypeError):
+        sp.unpack_vec(lat, torch.zeros(4096, dtype=torch.uint8), "f32")
+    with pytest.raises(TypeError):
+        sp.unpack_vec(lat, torch.zeros(16, dtype=torch.float32), "f32")

@@ -158,3 +158,26 @@ def test_dslash_largest_lattice_point_sources(prec):
         y[idx, col] = 0
         assert torch.count_nonzero(y).item() == 0
         del v, y
+
+
+def test_packed_buffer_sizes_and_devices_checked():
+    """A packed vector of another format or lattice, or an output buffer too small, is refused by the binding
+    before the library is called, instead of letting the kernel read or write past the buffer."""
+    dims = (4, 4, 4, 4)
+    G = gauge(dims, li.haar_links(dims, 91), "f32", 12)
+    v = to_dev(li.gaussian_vector(G.lat.Vh, 92))
+    p16 = sp.pack_vec(G.lat, v, "f16")  # 16 B per site against 24 B for FP32
+    with pytest.raises(ValueError):
+        sp.dslash_packed(G, "f32", p16, 1)
+    p32 = sp.pack_vec(G.lat, v, "f32")
+    with pytest.raises(ValueError):
+        sp.dslash_packed(G, "f32", p32, 1, out=torch.empty(16, dtype=torch.uint8, device="cuda:0"))
+    with pytest.raises(ValueError):
+        sp.dslash_packed(G, "f32", p32[:-8], 1)
+    with pytest.raises(ValueError):
+        sp.unpack_vec(G.lat, p16, "f32")
+    with pytest.raises(TypeError):
+        sp.dslash_packed(G, "f32", p32.cpu(), 1)
+    out = sp.dslash_packed(G, "f32", p32, 1)  # the right buffers still work
+    ref = oracle.dslash_eo(dims, li.haar_links(dims, 91), to_host(v), 1)
+    assert rel_err_max(to_host(sp.unpack_vec(G.lat, out, "f32")), ref) <= DSLASH_TOL["f32"]
