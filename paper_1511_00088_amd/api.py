@@ -171,6 +171,8 @@ def cg_solve(gauge: Gauge, mass: float, b: torch.Tensor, tol: float = 1e-8, inne
     inner_p = _prec(inner)
     if inner_p != L.SP_F64 and inner_p != gauge.lo_prec:
         raise ValueError("the gauge field's low-precision packing must match the inner precision")
+    if out is not None:
+        _check_c128(out, (lat.Vh, 3), "out")
     x = out if out is not None else torch.empty_like(b)
     if x0 is not None:
         _check_c128(x0, (lat.Vh, 3), "x0")

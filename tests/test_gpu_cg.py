@@ -144,6 +144,19 @@ def test_solves_from_two_host_threads_match_sequential():
             assert st.converged and bool((x == ref[i]).all())
 
 
+def test_out_buffer_checked():
+    """A caller's output buffer of the wrong shape is refused before the solve writes through its pointer; one
+    of the right shape receives the solution and is returned."""
+    dims = (4, 4, 4, 4)
+    G = gauge(dims, li.haar_links(dims, 420), "f32")
+    b = to_dev(li.gaussian_even_source(dims, 421))
+    with pytest.raises(ValueError):
+        sp.cg_solve(G, 0.1, b, tol=1e-8, out=torch.empty((10, 3), dtype=torch.complex128, device="cuda:0"))
+    out = torch.empty_like(b)
+    x, st = sp.cg_solve(G, 0.1, b, tol=1e-8, out=out)
+    assert x is out and st.converged
+
+
 _CFG1 = {}
 
 
