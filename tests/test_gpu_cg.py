@@ -37,7 +37,9 @@ def test_cfg0_fp64(use_graph):
     assert rel_err_2(x, xr) <= 1e-8
 
 
-SMALL = [((8, 8, 8, 8), 0), ((6, 8, 4, 12), 1)]
+# the last two have a direction of extent 2, where both hops of that direction reach the same neighbour
+# (with the antiperiodic sign applied from each side in t), and (2, 4, 6, 8) has one site per checkerboard row
+SMALL = [((8, 8, 8, 8), 0), ((6, 8, 4, 12), 1), ((2, 4, 6, 8), 1), ((4, 4, 2, 2), 1)]
 
 
 @pytest.mark.parametrize("inner,recon", [("f64", 18), ("f32", 18), ("f32", 12), ("f16", 18), ("f16", 12),
