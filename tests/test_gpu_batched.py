@@ -82,10 +82,12 @@ def test_batched_masses_two_decades_apart(inner, recon):
 @pytest.mark.parametrize("inner,recon", [("f32", 12), ("f16", 18), ("bf16", 12), ("f64", 18)])
 def test_batched_antiperiodic_groups_beside_periodic(inner, recon):
     """Groups whose time boundary differs in the same launches: one link field on 6x8x4x12 packed with
-    antiperiodic and with periodic time, and an antiperiodic 4^4 field. Every system against the oracle's
+    antiperiodic and with periodic time, an antiperiodic 4^4 field and an antiperiodic 2x4x6x2 field (extent 2
+    in x and t). Every system against the oracle's
     solution with its own boundary condition, and its true residual recomputed by the oracle."""
     announce(f"batched antiperiodic and periodic groups {inner} r{recon}")
-    specs = [((6, 8, 4, 12), 1, 350, [0.03, 0.08]), ((6, 8, 4, 12), 0, 350, [0.05]), ((4, 4, 4, 4), 1, 351, [0.1, 0.02])]
+    specs = [((6, 8, 4, 12), 1, 350, [0.03, 0.08]), ((6, 8, 4, 12), 0, 350, [0.05]), ((4, 4, 4, 4), 1, 351, [0.1, 0.02]),
+             ((2, 4, 6, 2), 1, 352, [0.04])]
     systems, host = [], []
     k = 0
     for dims, bc, seed, masses in specs:

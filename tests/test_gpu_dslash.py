@@ -20,7 +20,8 @@ COMBOS = [("f64", 18), ("f32", 18), ("f32", 12), ("f16", 18), ("f16", 12), ("bf1
 
 
 @pytest.mark.parametrize("prec,recon", COMBOS)
-@pytest.mark.parametrize("dims,bc_t", [((4, 4, 4, 4), 0), ((8, 6, 4, 10), 1), ((2, 2, 2, 2), 0)])
+@pytest.mark.parametrize("dims,bc_t", [((4, 4, 4, 4), 0), ((8, 6, 4, 10), 1), ((2, 2, 2, 2), 0), ((2, 2, 2, 2), 1),
+                                       ((2, 6, 4, 2), 1)])
 def test_dslash_parity_small(prec, recon, dims, bc_t):
     announce(f"dslash {prec} r{recon} dims={dims} bc_t={bc_t}")
     V = li.volume(dims)
