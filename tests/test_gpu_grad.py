@@ -13,7 +13,7 @@ from gpu_common import DEV, announce, gauge, to_dev, to_host
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("dims,bc_t", [((4, 4, 4, 4), 0), ((6, 4, 8, 4), 1)])
+@pytest.mark.parametrize("dims,bc_t", [((4, 4, 4, 4), 0), ((6, 4, 8, 4), 1), ((4, 2, 6, 2), 1)])
 def test_force_kernel_matches_oracle(dims, bc_t):
     announce(f"force dims={dims} bc_t={bc_t}")
     U = li.near_identity_links(dims, 0.3, 401)
