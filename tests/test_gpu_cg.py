@@ -370,11 +370,12 @@ def test_solution_scales_with_the_source(inner, recon):
 
 @pytest.mark.parametrize("inner", ["f32", "f16", "bf16"])
 def test_fast_converging_systems(inner):
-    # heavy masses and a 2^4 lattice converge by many decades within one 25-iteration chunk; the recursive
-    # residual must not be left to run far below the true one until the chunk end (that once cost ~800
-    # iterations at m = 1 and lost convergence with delta = 0): every case converges to the oracle's
-    # solution in a bounded number of iterations, with and without the delta trigger
-    for dims, kind, m, cap in (((8, 8, 8, 8), "near", 1.0, 60), ((8, 8, 8, 8), "near", 0.3, 120),
+    # heavy masses (up to m = 30, where A is 900 + [0, 16]) and a 2^4 lattice converge by many decades within
+    # one 25-iteration chunk; the recursive residual must not be left to run far below the true one until the
+    # chunk end (that once cost ~800 iterations at m = 1 and lost convergence with delta = 0): every case
+    # converges to the oracle's solution in a bounded number of iterations, with and without the delta trigger
+    for dims, kind, m, cap in (((8, 8, 8, 8), "near", 30.0, 40), ((8, 8, 8, 8), "near", 1.0, 60),
+                               ((8, 8, 8, 8), "near", 0.3, 120),
                                ((2, 2, 2, 2), "haar", 0.1, 250), ((2, 2, 2, 2), "near", 0.1, 200)):
         U = li.haar_links(dims, 221) if kind == "haar" else li.near_identity_links(dims, 0.3, 221)
         b = li.gaussian_even_source(dims, 222)
