@@ -23,7 +23,9 @@
  *    enqueue on it and return once it has reached their end (they need convergence decisions and
  *    statistics on the host).
  *  - Errors: the return value is an sp_status. Negative codes leave outputs unspecified;
- *    SP_NOT_CONVERGED (positive) leaves the best solution and valid statistics. sp_strerror() names a
+ *    SP_NOT_CONVERGED (positive: the iteration cap, or a true residual that did not improve over seven
+ *    reliable updates in a row) leaves the solution of the last reliable update, whose true residual the
+ *    statistics report (it need not be the smallest seen). sp_strerror() names a
  *    code, sp_last_error() gives the detailed message of the calling thread's last failure (including
  *    the HIP error string for SP_ERR_HIP). No C++ exception crosses this interface.
  *  - Not reentrant on one workspace: two calls that share a workspace must not overlap.
@@ -78,7 +80,9 @@ typedef struct {
  *  max_iter   iteration cap (> 0)
  *  inner      precision of the iterated vectors and links: SP_F64 gives plain FP64 CG; SP_F32, SP_F16,
  *             SP_BF16 give mixed precision with FP64 reliable updates (true residual recomputed from an
- *             FP64 solution that accumulates the low-precision increments)
+ *             FP64 solution that accumulates the low-precision increments). 16-bit storage needs a
+ *             moderate condition number: on near-identity fields it converges at m = 0.01 (condition
+ *             number ~1.6e5) but stalls near m = 1e-3 (~1.6e7), where SP_F32 and SP_F64 still converge
  *  delta      reliable update when |r_iterated| < delta * |r at the last update| (0 disables; ignored
  *             for SP_F64; checked at the end of each poll chunk)
  *  ru_every   reliable update at least every ru_every iterations (ignored for SP_F64; <= 0 picks 100;

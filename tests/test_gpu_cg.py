@@ -159,6 +159,31 @@ def test_out_buffer_checked():
     assert x is out and st.converged
 
 
+def test_light_mass_limits_of_16bit_storage():
+    """m = 1e-3 on 8^4 (condition number ~1.6e7): FP32 iterations with FP64 reliable updates still reach the FP64
+    solve's answer. 16-bit storage stalls in this regime; whatever it does, its report is truthful: converged
+    and status agree with the true residual of the solution it returns, recomputed by the oracle, and the
+    reported residual is that one."""
+    dims = (8, 8, 8, 8)
+    U = li.near_identity_links(dims, 0.3, 231)
+    b = li.gaussian_even_source(dims, 232)
+    m = 1e-3
+    x64, s64 = sp.cg_solve(gauge(dims, U, "f64"), m, to_dev(b), tol=1e-8, inner="f64")
+    x32, s32 = sp.cg_solve(gauge(dims, U, "f32", 12), m, to_dev(b), tol=1e-8, inner="f32")
+    announce(f"m=1e-3: FP64 {s64.iters} iterations, FP32 {s32.iters} ({s32.reliable_updates} updates)")
+    assert s64.converged and s32.converged
+    assert rel_err_2(to_host(x32), to_host(x64)) <= 1e-6
+    for inner in ("f16", "bf16"):
+        x, st = sp.cg_solve(gauge(dims, U, inner, 12), m, to_dev(b), tol=1e-8, inner=inner, max_iter=20000)
+        res = _true_resid(dims, U, m, b, to_host(x))
+        announce(f"  {inner}: iters={st.iters} status={st.status} reported {st.true_rel_resid:.3e} oracle {res:.3e}")
+        assert abs(res - st.true_rel_resid) <= 1e-6 * res
+        if st.converged:
+            assert st.status == 0 and res <= 1.01e-8
+        else:
+            assert st.status == 1 and res > 1e-8
+
+
 _CFG1 = {}
 
 
