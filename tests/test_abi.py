@@ -166,3 +166,19 @@ def test_packed_buffers_checked_before_any_call():
         sp.unpack_vec(lat, torch.zeros(4096, dtype=torch.uint8), "f32")
     with pytest.raises(TypeError):
         sp.unpack_vec(lat, torch.zeros(16, dtype=torch.float32), "f32")
+
+
+def test_roofline_bytes_match_the_packed_layout():
+    # the benchmark's algorithmic bytes per site come from per-link and per-vector sizes: they must be what
+    # the library actually packs (host queries only), and the flop count is that of 8 complex 3x3 mat-vecs
+    # (9 complex products, 6 complex sums) and 7 colour-vector sums
+    import bench
+
+    lat = sp.Lattice((4, 4, 4, 8))
+    for (prec, recon), per_link in bench.LINK_BYTES.items():
+        assert lat.gauge_bytes(prec, recon) == 4 * lat.V * per_link
+    for prec, per_site in bench.VEC_BYTES.items():
+        assert lat.vec_bytes(prec) == lat.Vh * per_site
+    assert bench.FLOP_PER_SITE == 8 * (9 * 6 + 6 * 2) + 7 * 6
+    assert bench.dslash_bytes_per_site("f32", 12) == 432
+    assert bench.iteration_bytes_per_site("f32", 12) == 1032
