@@ -260,7 +260,8 @@ int sp_full_solve(const sp_geom* g, const sp_gauge* U, double mass, const double
 int sp_tune_dslash(const sp_geom* g, const sp_gauge* U, int prec, void* in, void* out, void* stream,
                    double* best_ms);
 
-/* Save / load the tuned launches as JSON text (path on the host file system). Load merges entries. */
+/* Save / load the tuned launches as JSON text (path on the host file system). Load merges the file's
+ * entries into the table; a malformed or truncated file returns SP_ERR_INVALID_ARG and changes nothing. */
 int sp_tune_save(const char* path);
 int sp_tune_load(const char* path);
 

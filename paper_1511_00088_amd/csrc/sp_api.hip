@@ -946,7 +946,8 @@ int sp_tune_load(const char* path) {
     std::stringstream ss;
     ss << f.rdbuf();
     const std::string txt = ss.str();
-    std::lock_guard<std::mutex> lock(g_mu);
+    // entries are parsed into a temporary table and take effect only if the whole file parses
+    std::map<std::string, LaunchCfg> parsed;
     size_t pos = 0;
     while ((pos = txt.find('"', pos)) != std::string::npos) {
         const size_t end = txt.find('"', pos + 1);
@@ -956,14 +957,18 @@ int sp_tune_load(const char* path) {
         int nt = 0, remap = 0;
         const size_t brace = txt.find('{', end);
         if (brace == std::string::npos) break;
-        if (sscanf(txt.c_str() + brace, "{\"nt\": %d, \"remap\": %d}", &nt, &remap) != 2)
+        const size_t close = txt.find('}', brace);
+        if (close == std::string::npos ||
+            sscanf(txt.c_str() + brace, "{\"nt\": %d, \"remap\": %d}", &nt, &remap) != 2)
             return fail(SP_ERR_INVALID_ARG, "malformed tuning entry for %s", key.c_str());
         if (nt != 64 && nt != 128 && nt != 256) return fail(SP_ERR_INVALID_ARG, "bad block size %d", nt);
         c.nt = nt;
         c.remap = remap ? 1 : 0;
-        g_tune[key] = c;
-        pos = txt.find('}', brace) + 1;
+        parsed[key] = c;
+        pos = close + 1;
     }
+    std::lock_guard<std::mutex> lock(g_mu);
+    for (const auto& kv : parsed) g_tune[kv.first] = kv.second;
     return SP_OK;
 }
 

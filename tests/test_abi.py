@@ -182,3 +182,28 @@ def test_roofline_bytes_match_the_packed_layout():
     assert bench.FLOP_PER_SITE == 8 * (9 * 6 + 6 * 2) + 7 * 6
     assert bench.dslash_bytes_per_site("f32", 12) == 432
     assert bench.iteration_bytes_per_site("f32", 12) == 1032
+
+
+def test_tune_load_rejects_truncated_and_partial_files(tmp_path):
+    # an entry cut off before its closing brace once sent the reader back to the start of the file for
+    # ever: run it in a child process with a time limit, then check that a file whose second entry is bad
+    # changes nothing (the first entry is not applied)
+    import subprocess
+    import sys
+
+    trunc = tmp_path / "trunc.json"
+    trunc.write_text('{\n  "8x8x8x8/l1/r12/v1": {"nt": 128, "remap": 1')
+    code = ("import sys; sys.path.insert(0, %r); from paper_1511_00088_amd import _lib; "
+            "print(_lib.load().sp_tune_load(%r.encode()))" % (ROOT, str(trunc)))
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=60)
+    assert r.returncode == 0 and int(r.stdout.split()[-1]) == _lib.SP_ERR_INVALID_ARG
+
+    lib = _lib.load()
+    lib.sp_release_cache()
+    part = tmp_path / "part.json"
+    part.write_text('{\n  "6x6x6x6/l1/r12/v1": {"nt": 64, "remap": 1},\n  "6x6x6x6/l1/r18/v1": {"nt": 96, "remap": 0}\n}\n')
+    assert lib.sp_tune_load(str(part).encode()) == _lib.SP_ERR_INVALID_ARG
+    out = tmp_path / "out.json"
+    assert lib.sp_tune_save(str(out).encode()) == 0
+    assert "6x6x6x6" not in out.read_text()
+    lib.sp_release_cache()
