@@ -175,6 +175,27 @@ def test_batched_full_size_workload_vs_oracle_samples():
     assert err <= 1e-6
 
 
+def test_batched_more_than_64_groups():
+    """67 systems, each on its own 4^4 gauge field, so 67 groups: a block finds its group with one ballot per
+    64 groups, and this crosses into the second one; every system against the oracle."""
+    dims = (4, 4, 4, 4)
+    systems, host = [], []
+    for i in range(67):
+        U = li.near_identity_links(dims, 0.3, 500 + i)
+        b = li.gaussian_even_source(dims, 600 + i)
+        m = 0.05 + 0.001 * i
+        systems.append((gauge(dims, U, "f32", 12), m, to_dev(b)))
+        host.append((U, m, b))
+    xs, stats = sp.cg_solve_batched(systems, tol=1e-9, inner="f32")
+    worst = 0.0
+    for (U, m, b), x, st in zip(host, xs, stats):
+        xr, _, _, _ = oracle.cg_solve(dims, U, m, b, tol=1e-12)
+        assert st.converged
+        worst = max(worst, rel_err_2(to_host(x), xr))
+    announce(f"67 groups: worst error against the oracle {worst:.2e}")
+    assert worst <= 1e-7
+
+
 def test_batched_deterministic():
     systems, _ = _batch("f32")
     xa, sa = sp.cg_solve_batched(systems, tol=1e-8, inner="f32")
