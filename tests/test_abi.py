@@ -207,3 +207,20 @@ def test_tune_load_rejects_truncated_and_partial_files(tmp_path):
     assert lib.sp_tune_save(str(out).encode()) == 0
     assert "6x6x6x6" not in out.read_text()
     lib.sp_release_cache()
+
+
+def test_product_package_never_reaches_the_oracle():
+    # the oracle is test infrastructure: no source of the package (Python, HIP, headers, build) names it,
+    # and importing the package does not load it
+    import subprocess
+    import sys
+
+    pkg = os.path.join(ROOT, "paper_1511_00088_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for name in files:
+            if name.endswith((".py", ".hip", ".h", ".json")):
+                with open(os.path.join(dirpath, name), encoding="utf-8") as fh:
+                    assert "oracle" not in fh.read(), os.path.join(dirpath, name)
+    code = "import sys; sys.path.insert(0, %r); import paper_1511_00088_amd; print('oracle' in sys.modules)" % ROOT
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0 and r.stdout.split()[-1] == "False"
