@@ -827,9 +827,17 @@ int sp_tune_dslash(const sp_geom* g, const sp_gauge* U, int prec, void* in, void
     int rc = dslash_desc(g, U, prec, in, out, 1, &G, &d, &lp, &recon);
     if (rc) return rc;
     hipStream_t s = (hipStream_t)stream;
-    hipEvent_t e0, e1;
-    HIP_TRY(hipEventCreate(&e0));
-    HIP_TRY(hipEventCreate(&e1));
+    // timing events, destroyed on every return path
+    struct TimingEvents {
+        hipEvent_t a = nullptr, b = nullptr;
+        ~TimingEvents() {
+            if (a) (void)hipEventDestroy(a);
+            if (b) (void)hipEventDestroy(b);
+        }
+    } ev;
+    HIP_TRY(hipEventCreate(&ev.a));
+    HIP_TRY(hipEventCreate(&ev.b));
+    hipEvent_t e0 = ev.a, e1 = ev.b;
     const int nts[3] = {64, 128, 256};
     const int reps = 20;
     const int use64 = prec == SP_F64;
@@ -913,8 +921,6 @@ int sp_tune_dslash(const sp_geom* g, const sp_gauge* U, int prec, void* in, void
         HIP_TRY(e);
         HIP_TRY(es);
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     {
         std::lock_guard<std::mutex> lock(g_mu);
         g_tune[tune_key(G, lp, recon, prec)] = best;
