@@ -172,8 +172,9 @@ int sp_cg_solve(const sp_geom* g, const sp_gauge* U, double mass, const double* 
  * to 4 right-hand sides; all groups advance in one launch per kernel, captured in a hipGraph per chunk
  * of iterations; converged systems stop updating while the others continue. Groups may differ in volume
  * and time boundary; a zero b_e stops at the first residual check with x_e = 0. stats: host array of nsys
- * (nullable). Returns SP_OK if every system converged, SP_NOT_CONVERGED if any did not, or an error.
- * Synchronous with respect to stream. */
+ * (nullable). Returns SP_OK if every system converged, SP_NOT_CONVERGED if any did not, or an error. When
+ * some systems break down (SP_ERR_BREAKDOWN), stats[i].status names them and the other systems' x_e and
+ * statistics are valid: reductions and states are kept per system. Synchronous with respect to stream. */
 int sp_cg_solve_batched(int nsys, const sp_system* systems, const sp_cg_params* params,
                         sp_cg_stats* stats, void* ws, size_t ws_bytes, void* stream);
 

@@ -196,6 +196,41 @@ def test_batched_more_than_64_groups():
     assert worst <= 1e-7
 
 
+def test_batched_breakdown_of_one_system_leaves_the_others_solved():
+    """A NaN in one source breaks that system down. The call returns SP_ERR_BREAKDOWN, and through the C-ABI
+    the per-system statistics name that system while the two others of its group are solved to the oracle's
+    answer: reductions and states are per system, so nothing leaks between them."""
+    import ctypes
+
+    from paper_1511_00088_amd import _lib as L
+
+    dims = (4, 4, 4, 8)
+    U = li.near_identity_links(dims, 0.3, 430)
+    G = gauge(dims, U, "f32", 12)
+    bs = [li.gaussian_even_source(dims, 431 + i) for i in range(3)]
+    bs[1] = bs[1].copy()
+    bs[1][5, 2] = np.nan
+    ms = [0.05, 0.05, 0.02]
+    bd = [to_dev(b) for b in bs]
+    xs = [torch.empty_like(b) for b in bd]
+    arr = (L.sp_system * 3)()
+    for i in range(3):
+        arr[i] = L.sp_system(ctypes.pointer(G.lat.geom), ctypes.pointer(G.struct), ms[i], bd[i].data_ptr(),
+                             xs[i].data_ptr())
+    prm = L.sp_cg_params(1e-9, 100000, L.SP_F32, 0.1, 0, 0, 0, 1)
+    lib = L.load()
+    nbytes = lib.sp_cg_workspace_bytes(3, arr, ctypes.byref(prm))
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0")
+    st = (L.sp_cg_stats * 3)()
+    rc = lib.sp_cg_solve_batched(3, arr, ctypes.byref(prm), st, ctypes.c_void_p(ws.data_ptr()),
+                                 ctypes.c_size_t(nbytes), ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    assert rc == L.SP_ERR_BREAKDOWN
+    assert [st[i].status for i in range(3)] == [0, L.SP_ERR_BREAKDOWN, 0]
+    for i in (0, 2):
+        xr, _, _, _ = oracle.cg_solve(dims, U, ms[i], bs[i], tol=1e-12)
+        assert st[i].converged and rel_err_2(to_host(xs[i]), xr) <= 1e-7
+
+
 def test_batched_deterministic():
     systems, _ = _batch("f32")
     xa, sa = sp.cg_solve_batched(systems, tol=1e-8, inner="f32")
