@@ -194,8 +194,10 @@ def cg_solve(gauge: Gauge, mass: float, b: torch.Tensor, tol: float = 1e-8, inne
 
 def cg_solve_batched(systems, tol: float = 1e-8, inner="f32", max_iter: int = 100000, delta: float = 0.1,
                      ru_every: int = 0, poll_chunk: int = 0, use_graph: bool = True,
-                     workspace: Workspace | None = None):
-    """Solve many systems together. systems: list of (Gauge, mass, b). Returns (list of x, list of stats)."""
+                     workspace: Workspace | None = None, raise_on_breakdown: bool = True):
+    """Solve many systems together. systems: list of (Gauge, mass, b). Returns (list of x, list of stats).
+    With raise_on_breakdown=False a breakdown of some systems does not raise: their stats carry the status
+    SP_ERR_BREAKDOWN and the other systems' solutions and stats are valid."""
     n = len(systems)
     if n == 0:
         return [], []
@@ -219,7 +221,8 @@ def cg_solve_batched(systems, tol: float = 1e-8, inner="f32", max_iter: int = 10
     ws = (workspace or _default_ws).get(nbytes, dev)
     st = (L.sp_cg_stats * n)()
     rc = lib.sp_cg_solve_batched(n, arr, ctypes.byref(prm), st, _ptr(ws), ctypes.c_size_t(ws.numel()), _stream())
-    L.check(rc, "sp_cg_solve_batched", allow_not_converged=True)
+    if not (rc == L.SP_ERR_BREAKDOWN and not raise_on_breakdown):
+        L.check(rc, "sp_cg_solve_batched", allow_not_converged=True)
     return xs, [_stats(s) for s in st]
 
 

@@ -229,6 +229,15 @@ def test_batched_breakdown_of_one_system_leaves_the_others_solved():
     for i in (0, 2):
         xr, _, _, _ = oracle.cg_solve(dims, U, ms[i], bs[i], tol=1e-12)
         assert st[i].converged and rel_err_2(to_host(xs[i]), xr) <= 1e-7
+    # the binding: raises by default, returns every system's result on request
+    sysl = [(G, m, b) for m, b in zip(ms, bd)]
+    with pytest.raises(sp.StagError) as e:
+        sp.cg_solve_batched(sysl, tol=1e-9, inner="f32")
+    assert e.value.code == L.SP_ERR_BREAKDOWN
+    xp, sp_st = sp.cg_solve_batched(sysl, tol=1e-9, inner="f32", raise_on_breakdown=False)
+    assert [q.status for q in sp_st] == [0, L.SP_ERR_BREAKDOWN, 0]
+    for i in (0, 2):
+        assert bool((xp[i] == xs[i]).all())
 
 
 def test_batched_deterministic():
