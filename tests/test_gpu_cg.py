@@ -94,6 +94,10 @@ def test_not_converged_and_breakdown():
     G = gauge(dims, U, "f32")
     x, st = sp.cg_solve(G, 0.01, to_dev(b), tol=1e-10, inner="f32", max_iter=3)
     assert st.status == 1 and not st.converged and st.iters == 3
+    # the autograd glue asks for this, so that an unconverged solve never yields a gradient silently
+    with pytest.raises(sp.StagError) as e:
+        sp.cg_solve(G, 0.01, to_dev(b), tol=1e-10, inner="f32", max_iter=3, raise_on_not_converged=True)
+    assert e.value.code == 1
     bn = b.copy()
     bn[3, 1] = np.nan
     with pytest.raises(sp.StagError) as e:
