@@ -85,6 +85,9 @@ def test_warm_start():
     xr, _, _, _ = oracle.cg_solve(dims, U, 0.05, b, tol=1e-12)
     assert s1.converged and s2.converged
     assert rel_err_2(to_host(x2), xr) <= 1e-8
+    # a start that already meets the tolerance stops at the first residual check and is returned unchanged
+    x3, s3 = sp.cg_solve(G, 0.05, to_dev(b), tol=1e-8, inner="f32", x0=x2)
+    assert s3.converged and s3.iters == 0 and bool((x3 == x2).all())
 
 
 def test_not_converged_and_breakdown():
