@@ -78,11 +78,13 @@ __device__ __forceinline__ const SysDev& sys_of(const DescBatch& d, int i) { ret
 
 // Block order: with remap, consecutive logical blocks (neighbouring lattice slabs) go to the same XCD.
 // The hardware hands block b to XCD b % 8; logical block = start of that XCD's contiguous range + b / 8.
-__device__ __forceinline__ int logical_block(int remap) {
-    const int b = blockIdx.x, nb = gridDim.x;
-    if (!remap) return b;
+// A bijection of [0, nb) for every nb (XCD x owns nb / 8 blocks, plus one for the first nb % 8 XCDs).
+__host__ __device__ __forceinline__ int remap_block(int b, int nb) {
     const int q = nb >> 3, rem = nb & 7, x = b & 7, i = b >> 3;
-    return x * q + min(x, rem) + i;
+    return x * q + (x < rem ? x : rem) + i;
+}
+__device__ __forceinline__ int logical_block(int remap) {
+    return remap ? remap_block(blockIdx.x, gridDim.x) : (int)blockIdx.x;
 }
 
 // Whether a launch gated by `gate` works on a system whose state flags are f.
