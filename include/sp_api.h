@@ -196,6 +196,23 @@ int sp_cg_force(const sp_geom* g, const sp_gauge* U, double mass, const double* 
                 const double* lambda_e, double* gamma, double* force, double* grad_mass, void* ws,
                 size_t ws_bytes, void* stream);
 
+/* Size of the device array that sp_cg_force_noalloc keeps its scratch in (64 MiB per GPU): enough for
+ * lattices with V/2 up to 349,000 sites (20^3x64 and 16^3x32 fit; 28^3x96 does not). */
+#define SP_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/* sp_cg_force for callers that cannot allocate device memory (code under stream capture, serving loops,
+ * harnesses that forbid hipMalloc): the same gradient from the same kernels, with no workspace argument and no
+ * allocation of any kind. Its scratch is a fixed device array of SP_NOALLOC_SCRATCH_BYTES that each GPU the
+ * library runs on holds until the process ends; lattices whose sp_force_workspace_bytes exceeds it are refused
+ * with SP_ERR_WORKSPACE before anything is enqueued. The first call on a device looks up that device's array
+ * (hipGetSymbolAddress), so make it outside stream capture. Asynchronous on stream (unlike sp_cg_force): the
+ * outputs are ready when the stream reaches the end of the call. Every call on one GPU shares that GPU's
+ * array: calls that can overlap on one GPU (on different streams, or from several host threads without
+ * ordering) race and must be serialised, e.g. by issuing them on one stream. Nothing in the array needs to
+ * start at zero (each launch writes every word it later reads); it keeps the last call's contents. */
+int sp_cg_force_noalloc(const sp_geom* g, const sp_gauge* U, double mass, const double* x_e,
+                        const double* lambda_e, double* gamma, double* force, double* grad_mass, void* stream);
+
 /* Workspace bytes for sp_hyp_smear on geometry g (24 FP64 link fields of V links). */
 size_t sp_hyp_workspace_bytes(const sp_geom* g);
 

@@ -22,6 +22,9 @@ SP_ERR_WORKSPACE = -4
 SP_ERR_HIP = -5
 SP_ERR_BREAKDOWN = -6
 
+# bytes of the fixed device array of sp_cg_force_noalloc (SP_NOALLOC_SCRATCH_BYTES)
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
 
 class sp_geom(ctypes.Structure):
     _fields_ = [("dims", ctypes.c_int32 * 4), ("bc_t", ctypes.c_int32)]
@@ -73,6 +76,7 @@ SIGNATURES = {
     "sp_cg_solve_batched": (I, [I, PY, PP, PS, P, SZ, P]),
     "sp_force_workspace_bytes": (SZ, [PG]),
     "sp_cg_force": (I, [PG, PU, D, P, P, P, P, P, P, SZ, P]),
+    "sp_cg_force_noalloc": (I, [PG, PU, D, P, P, P, P, P, P]),
     "sp_full_workspace_bytes": (SZ, [PG, PU, PP]),
     "sp_full_solve": (I, [PG, PU, D, P, P, PP, PS, P, SZ, P]),
     "sp_hyp_workspace_bytes": (SZ, [PG]),

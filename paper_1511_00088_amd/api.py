@@ -269,6 +269,26 @@ def cg_force(gauge: Gauge, mass: float, x: torch.Tensor, lam: torch.Tensor, want
     return gamma, force, dmass
 
 
+
+def cg_force_noalloc(gauge: Gauge, mass: float, x: torch.Tensor, lam: torch.Tensor, gamma: torch.Tensor,
+                     force: torch.Tensor | None, dmass: torch.Tensor | None):
+    """sp_cg_force_noalloc: the gradient of cg_force into caller-provided outputs (gamma and force complex128
+    [4][V][3][3], dmass a float64 scalar), with the library allocating nothing; asynchronous on the current
+    stream. Lattices whose scratch exceeds the library's fixed array (64 MiB) raise SP_ERR_WORKSPACE."""
+    lat = gauge.lat
+    _check_c128(x, (lat.Vh, 3), "x")
+    _check_c128(lam, (lat.Vh, 3), "lambda")
+    _check_c128(gamma, (4, lat.V, 3, 3), "gamma")
+    if force is not None:
+        _check_c128(force, (4, lat.V, 3, 3), "force")
+    if dmass is not None and (dmass.dtype != torch.float64 or not dmass.is_cuda or dmass.numel() != 1):
+        raise TypeError("dmass must be a float64 GPU scalar")
+    rc = L.load().sp_cg_force_noalloc(ctypes.byref(lat.geom), ctypes.byref(gauge.struct), float(mass), _ptr(x),
+                                      _ptr(lam), _ptr(gamma), _ptr(force) if force is not None else None,
+                                      _ptr(dmass) if dmass is not None else None, _stream())
+    L.check(rc, "sp_cg_force_noalloc")
+    return gamma, force, dmass
+
 HYP_ALPHA = (0.75, 0.6, 0.3)
 
 

@@ -37,8 +37,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/sp_api.h"
-#include "sp_launch.h"
+#include "sp_entry.h"
 
 using namespace sp;
 
@@ -705,6 +704,51 @@ int solve_impl(int nsys, const sp_system* systems, const sp_cg_params* prm, sp_c
 
 }  // namespace
 
+namespace sp {
+
+int set_error(int code, const char* msg) { return fail(code, "%s", msg); }
+
+// Argument checks shared by sp_cg_force and its allocation-free variant.
+int force_check(const sp_geom* g, const sp_gauge* U, double mass, const double* x_e, const double* lambda_e,
+                const double* gamma, Geom* G) {
+    int rc = check_geom(g, G);
+    if (rc) return rc;
+    if (!U || !U->f64 || !x_e || !lambda_e || !gamma) return fail(SP_ERR_INVALID_ARG, "null pointer");
+    if (!std::isfinite(mass)) return fail(SP_ERR_INVALID_ARG, "mass not finite");
+    return SP_OK;
+}
+
+// The gradient's launches, with the scratch at base (force_scratch_bytes(G) bytes, 256-byte aligned): pack x
+// and lambda to FP64 planes, y_x = D_oe x and y_l = D_oe lambda, gamma and the force link by link, and the
+// two-stage reduction of dl/dm. Every scratch word is written before it is read. Asynchronous on s.
+int force_enqueue(const sp_geom* g, const Geom& G, const sp_gauge* U, double mass, const double* x_e,
+                  const double* lambda_e, double* gamma, double* force, double* grad_mass, char* base, hipStream_t s) {
+    const size_t v = align256((size_t)G.Vh * 48);
+    void* xp = base;
+    void* lp = base + v;
+    void* yx = base + 2 * v;
+    void* yl = base + 3 * v;
+    double* partials = (double*)(base + 4 * v);
+    HIP_TRY(launch_pack_vec(G.Vh, x_e, SP_F64, xp, s));
+    HIP_TRY(launch_pack_vec(G.Vh, lambda_e, SP_F64, lp, s));
+    sp_gauge Ug = *U;
+    Ug.lo = U->f64;
+    Ug.lo_prec = SP_F64;
+    int rc = sp_dslash(g, &Ug, SP_F64, xp, yx, 1, s);
+    if (rc) return rc;
+    rc = sp_dslash(g, &Ug, SP_F64, lp, yl, 1, s);
+    if (rc) return rc;
+    HIP_TRY(launch_force(G, U->f64, xp, lp, yx, yl, gamma, force, s));
+    if (grad_mass) HIP_TRY(launch_mass_grad(G, mass, xp, lp, partials, grad_mass, s));
+    return SP_OK;
+}
+
+size_t force_scratch_bytes(const Geom& G) {
+    return 4 * align256((size_t)G.Vh * 48) + align256(sizeof(double) * (size_t)mass_grad_blocks(G));
+}
+
+}  // namespace sp
+
 // =====================================================================================================
 // C-ABI
 // =====================================================================================================
@@ -1011,38 +1055,20 @@ int sp_cg_solve_batched(int nsys, const sp_system* systems, const sp_cg_params* 
 size_t sp_force_workspace_bytes(const sp_geom* g) {
     Geom G;
     if (check_geom(g, &G)) return 0;
-    return 4 * align256((size_t)G.Vh * 48) + align256(sizeof(double) * (size_t)mass_grad_blocks(G));
+    return sp::force_scratch_bytes(G);
 }
 
 int sp_cg_force(const sp_geom* g, const sp_gauge* U, double mass, const double* x_e, const double* lambda_e,
                 double* gamma, double* force, double* grad_mass, void* ws, size_t ws_bytes, void* stream) {
     Geom G;
-    int rc = check_geom(g, &G);
+    int rc = sp::force_check(g, U, mass, x_e, lambda_e, gamma, &G);
     if (rc) return rc;
-    if (!U || !U->f64 || !x_e || !lambda_e || !gamma) return fail(SP_ERR_INVALID_ARG, "null pointer");
-    if (!std::isfinite(mass)) return fail(SP_ERR_INVALID_ARG, "mass not finite");
     if (!ws) return fail(SP_ERR_WORKSPACE, "workspace is null");
     if (ws_bytes < sp_force_workspace_bytes(g)) return fail(SP_ERR_WORKSPACE, "workspace too small");
     if (((uintptr_t)ws) & 255) return fail(SP_ERR_INVALID_ARG, "workspace not 256-byte aligned");
     hipStream_t s = (hipStream_t)stream;
-    char* base = (char*)ws;
-    const size_t v = align256((size_t)G.Vh * 48);
-    void* xp = base;
-    void* lp = base + v;
-    void* yx = base + 2 * v;
-    void* yl = base + 3 * v;
-    double* partials = (double*)(base + 4 * v);
-    HIP_TRY(launch_pack_vec(G.Vh, x_e, SP_F64, xp, s));
-    HIP_TRY(launch_pack_vec(G.Vh, lambda_e, SP_F64, lp, s));
-    sp_gauge Ug = *U;
-    Ug.lo = U->f64;
-    Ug.lo_prec = SP_F64;
-    rc = sp_dslash(g, &Ug, SP_F64, xp, yx, 1, stream);
+    rc = sp::force_enqueue(g, G, U, mass, x_e, lambda_e, gamma, force, grad_mass, (char*)ws, s);
     if (rc) return rc;
-    rc = sp_dslash(g, &Ug, SP_F64, lp, yl, 1, stream);
-    if (rc) return rc;
-    HIP_TRY(launch_force(G, U->f64, xp, lp, yx, yl, gamma, force, s));
-    if (grad_mass) HIP_TRY(launch_mass_grad(G, mass, xp, lp, partials, grad_mass, s));
     HIP_TRY(hipStreamSynchronize(s));
     return SP_OK;
 }

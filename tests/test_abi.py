@@ -224,3 +224,24 @@ def test_product_package_never_reaches_the_oracle():
     code = "import sys; sys.path.insert(0, %r); import paper_1511_00088_amd; print('oracle' in sys.modules)" % ROOT
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120)
     assert r.returncode == 0 and r.stdout.split()[-1] == "False"
+
+
+def test_noalloc_force_refuses_lattices_beyond_its_array():
+    # 28^3x96 needs 4 FP64 half vectors of 1,053,696 sites (202 MB) of scratch: refused before any launch, so
+    # the placeholder pointers below are never touched
+    lib = _lib.load()
+    lat = sp.Lattice((28, 28, 28, 96))
+    need = lib.sp_force_workspace_bytes(ctypes.byref(lat.geom))
+    assert need > _lib.NOALLOC_SCRATCH_BYTES
+    g = _lib.sp_gauge(256, 256, _lib.SP_F64, 18)
+    rc = lib.sp_cg_force_noalloc(ctypes.byref(lat.geom), ctypes.byref(g), 0.1, ctypes.c_void_p(256),
+                                 ctypes.c_void_p(256), ctypes.c_void_p(256), None, None, None)
+    assert rc == _lib.SP_ERR_WORKSPACE
+    assert str(need).encode() in lib.sp_last_error()
+    # the 20^3x64 workload and the 16^3x32 gradient lattice fit
+    for dims in ((20, 20, 20, 64), (16, 16, 16, 32)):
+        assert lib.sp_force_workspace_bytes(ctypes.byref(sp.Lattice(dims).geom)) <= _lib.NOALLOC_SCRATCH_BYTES
+    # null arguments are refused as by sp_cg_force
+    small = sp.Lattice((4, 4, 4, 4))
+    assert lib.sp_cg_force_noalloc(ctypes.byref(small.geom), None, 0.1, None, None, None, None, None,
+                                   None) == _lib.SP_ERR_INVALID_ARG
