@@ -43,8 +43,10 @@
 extern "C" {
 #endif
 
-/* Storage precisions. Arithmetic is FP64 for SP_F64 and FP32 for the other three. */
-typedef enum { SP_F64 = 0, SP_F32 = 1, SP_F16 = 2, SP_BF16 = 3 } sp_prec;
+/* Storage precisions. Arithmetic is FP64 for SP_F64 and FP32 for the others. SP_I16 is 16-bit fixed point
+ * (q / 32767, rounded to nearest, absolute error <= 2^-16 for entries in [-1, 1]) and stores links only, for FP32
+ * iterations. */
+typedef enum { SP_F64 = 0, SP_F32 = 1, SP_F16 = 2, SP_BF16 = 3, SP_I16 = 4 } sp_prec;
 
 typedef enum {
     SP_OK = 0,
@@ -65,9 +67,10 @@ typedef struct {
 } sp_geom;
 
 /* A packed gauge field. f64: FP64 recon-18 packing (needed by every solve: true residuals);
- * lo: the packing of the inner precision lo_prec with recon 18 (all 9 complex entries) or 12 (first two
- * rows; the third is rebuilt as conj(row0 x row1), exact for SU(3) links). lo may equal f64 when
- * lo_prec is SP_F64. */
+ * lo: the packing used by the low-precision iterations, of precision lo_prec with recon 18 (all 9 complex
+ * entries) or 12 (first two rows; the third is rebuilt as conj(row0 x row1), exact for SU(3) links). lo_prec is
+ * the inner precision, or, for FP32 iterations, a 16-bit link storage (SP_F16, SP_BF16, SP_I16) with FP32
+ * vectors and arithmetic. lo may equal f64 when lo_prec is SP_F64. */
 typedef struct {
     const void* f64;
     const void* lo;
@@ -94,8 +97,9 @@ typedef struct {
  * A reliable update also runs whenever the iterated residual reaches tol, at the iteration cap, and (for
  * SP_F32, SP_F16, SP_BF16) when the iterated residual falls three decades below the true residual of the
  * last update. After
- * it, FP32 iterations keep the search direction (re-orthogonalised against the new residual); 16-bit
- * storage restarts it from the residual. */
+ * it, FP32 iterations on FP32 links keep the search direction (re-orthogonalised against the new residual);
+ * 16-bit storage of the vectors or of the links restarts it from the residual (a kept direction stalls when
+ * the rounded links move the operator by more than its smallest eigenvalue). */
 typedef struct {
     double tol;
     int32_t max_iter;
@@ -153,7 +157,8 @@ int sp_vec_pack(const sp_geom* g, const double* v_nat, int prec, void* out, void
 int sp_vec_unpack(const sp_geom* g, const void* v, int prec, double* v_nat, void* stream);
 
 /* Half staggered operator: out (parity out_parity) = D_{out_parity, 1-out_parity} in, both packed with
- * precision prec. Links: U->f64 when prec is SP_F64, else U->lo (U->lo_prec must equal prec).
+ * precision prec. Links: U->f64 when prec is SP_F64, else U->lo (U->lo_prec equal to prec, or a 16-bit link
+ * storage when prec is SP_F32).
  * Asynchronous on stream. This is the kernel the solver spends most of its time in. */
 int sp_dslash(const sp_geom* g, const sp_gauge* U, int prec, const void* in, void* out, int out_parity,
               void* stream);
@@ -282,6 +287,65 @@ int sp_tune_dslash(const sp_geom* g, const sp_gauge* U, int prec, void* in, void
  * entries into the table; a malformed or truncated file returns SP_ERR_INVALID_ARG and changes nothing. */
 int sp_tune_save(const char* path);
 int sp_tune_load(const char* path);
+
+/* One GPU's share of a lattice cut in time across GPUs: the decomposition of the paper's multi-GPU CG (Sec. 3,
+ * Fig. 2 and Table 2), where each GPU exchanges the boundary slices of the vector with its two neighbours in
+ * every operator application. local: X, Y, Z and the shard's time extent Tl (each even, >= 2); local.bc_t is
+ * the GLOBAL time boundary (the antiperiodic sign enters at global t = T - 1 -> 0). t0: global time of the
+ * shard's first slice (even); T: global time extent (even, t0 + Tl <= T). Local checkerboard index
+ * cb = global cb - t0 X Y Z / 2. One parity of one time slice is a face of F = X Y Z / 2 sites. */
+typedef struct {
+    sp_geom local;
+    int32_t t0;
+    int32_t T;
+} sp_shard;
+
+/* Bytes of one packed face (F sites) of vector precision prec; 0 on a bad shard. */
+size_t sp_shard_face_bytes(const sp_shard* s, int prec);
+
+/* Bytes of an extended shard vector of one parity: the packed planes of Vh + 2F sites, [ghost slice t0 - 1]
+ * [the shard's Tl slices][ghost slice t0 + Tl], local site cb at plane position F + cb. */
+size_t sp_shard_vec_bytes(const sp_shard* s, int prec);
+
+/* Natural local half vector (device, complex128 [Vh][3], local cb order) -> the local part of an extended
+ * vector (the ghost slices are left as they are). Asynchronous. */
+int sp_shard_vec_pack(const sp_shard* s, const double* v_nat, int prec, void* ext, void* stream);
+
+/* Face pack: copy the shard's lowest (side 0, local t = 0: for the neighbour below) or highest (side 1,
+ * t = Tl - 1: for the neighbour above) slice of an extended vector into face (sp_shard_face_bytes), word for
+ * word (no rounding; the FP16 per-site norms travel with their sites). Asynchronous. */
+int sp_face_pack(const sp_shard* s, int prec, const void* ext, int side, void* face, void* stream);
+
+/* Face unpack: copy a received face into the ghost slice below (side 0: the neighbour below's side-1 face) or
+ * above (side 1: the neighbour above's side-0 face) of an extended vector, word for word. Asynchronous. */
+int sp_face_unpack(const sp_shard* s, int prec, const void* face, int side, void* ext, void* stream);
+
+/* Bytes of the ghost t-links of a shard (U_t on global slice t0 - 1, both parities, 2F links) in the packed link
+ * format of (prec, recon). */
+size_t sp_shard_ghost_bytes(const sp_shard* s, int prec, int recon);
+
+/* Pack the ghost t-links: tlinks_nat = U_t(x, y, z, t0 - 1 mod T), device complex128 [X Y Z][3][3] in the order
+ * x + X (y + Y z). Exchanged once per gauge field. Asynchronous. */
+int sp_shard_ghost_pack(const sp_shard* s, const double* tlinks_nat, int prec, int recon, void* ghost, void* stream);
+
+/* Halo-fed half operator on a shard: out (local packed vector of parity out_parity, Vh sites, sp_vec_bytes of
+ * the local geometry) = D_{p,1-p} ext_in, where ext_in is an extended vector whose ghost slices hold the
+ * neighbours' faces, U is the shard's local packed gauge field (sp_gauge_pack on the local geometry, link
+ * precision as for sp_dslash) and ghost its ghost t-links in U's low-precision packing (FP64 recon 18 for
+ * prec SP_F64). part 0: every site; 1: the interior slices 1 .. Tl-2, which read no ghost and can run while the
+ * faces are in flight; 2: the boundary slices 0 and Tl - 1. With T = Tl (one shard) and each ghost holding the
+ * shard's own opposite face, this is sp_dslash on the periodic lattice. Asynchronous. */
+int sp_dslash_halo(const sp_shard* s, const sp_gauge* U, const void* ghost, int prec, const void* ext_in, void* out,
+                   int out_parity, int part, void* stream);
+
+/* Streaming-bandwidth probe, the attainable-bandwidth ceiling that the bandwidth-bound kernels are measured
+ * against (the paper's Sec. 4 / Table 3 reason about CG speed from memory bandwidth). kind 0 reads n16 16-byte
+ * words of a (writing one float per block of 256 lanes to b, sp_stream_out_bytes(n16, k) bytes), kind 1 copies
+ * a to b, kind 2 writes b = a + 0.5 c (FP32 lanes); each lane moves k whole 16-byte words (k = 1, 2, 4 or 8).
+ * a, b, c: device, 16-byte aligned, n16 words each (c only for kind 2). Asynchronous on stream; the caller
+ * times it. */
+size_t sp_stream_out_bytes(size_t n16, int k);
+int sp_stream_probe(int kind, int k, const void* a, void* b, const void* c, size_t n16, void* stream);
 
 /* Drop cached hipGraphs and tuning entries. */
 void sp_release_cache(void);

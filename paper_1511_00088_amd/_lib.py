@@ -10,8 +10,9 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libstagcg.so")
 
-SP_F64, SP_F32, SP_F16, SP_BF16 = 0, 1, 2, 3
-PREC = {"f64": SP_F64, "f32": SP_F32, "f16": SP_F16, "bf16": SP_BF16}
+SP_F64, SP_F32, SP_F16, SP_BF16, SP_I16 = 0, 1, 2, 3, 4
+# "i16": 16-bit fixed-point link storage (FP32 iterations only)
+PREC = {"f64": SP_F64, "f32": SP_F32, "f16": SP_F16, "bf16": SP_BF16, "i16": SP_I16}
 
 SP_OK = 0
 SP_NOT_CONVERGED = 1
@@ -28,6 +29,10 @@ NOALLOC_SCRATCH_BYTES = 64 << 20
 
 class sp_geom(ctypes.Structure):
     _fields_ = [("dims", ctypes.c_int32 * 4), ("bc_t", ctypes.c_int32)]
+
+
+class sp_shard(ctypes.Structure):
+    _fields_ = [("local", sp_geom), ("t0", ctypes.c_int32), ("T", ctypes.c_int32)]
 
 
 class sp_gauge(ctypes.Structure):
@@ -88,6 +93,16 @@ SIGNATURES = {
     "sp_tune_save": (I, [ctypes.c_char_p]),
     "sp_tune_load": (I, [ctypes.c_char_p]),
     "sp_release_cache": (None, []),
+    "sp_shard_face_bytes": (SZ, [ctypes.POINTER(sp_shard), I]),
+    "sp_shard_vec_bytes": (SZ, [ctypes.POINTER(sp_shard), I]),
+    "sp_shard_vec_pack": (I, [ctypes.POINTER(sp_shard), P, I, P, P]),
+    "sp_face_pack": (I, [ctypes.POINTER(sp_shard), I, P, I, P, P]),
+    "sp_face_unpack": (I, [ctypes.POINTER(sp_shard), I, P, I, P, P]),
+    "sp_shard_ghost_bytes": (SZ, [ctypes.POINTER(sp_shard), I, I]),
+    "sp_shard_ghost_pack": (I, [ctypes.POINTER(sp_shard), P, I, I, P, P]),
+    "sp_dslash_halo": (I, [ctypes.POINTER(sp_shard), PU, P, I, P, P, I, I, P]),
+    "sp_stream_out_bytes": (SZ, [SZ, I]),
+    "sp_stream_probe": (I, [I, I, P, P, P, SZ, P]),
 }
 
 _lib = None

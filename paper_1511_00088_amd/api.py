@@ -126,6 +126,13 @@ def dslash(gauge: Gauge, v: torch.Tensor, out_parity: int, prec="f64") -> torch.
     return unpack_vec(lat, dslash_packed(gauge, prec, pack_vec(lat, v, prec), out_parity), prec)
 
 
+def _links_serve(gauge: "Gauge", inner_p: int) -> bool:
+    """Whether the gauge field's low-precision packing can serve iterations of precision inner_p: its own
+    precision, or (for FP32 iterations) links stored in FP16, BF16 or 16-bit fixed point with FP32 vectors."""
+    return (inner_p == L.SP_F64 or inner_p == gauge.lo_prec
+            or (inner_p == L.SP_F32 and gauge.lo_prec in (L.SP_F16, L.SP_BF16, L.SP_I16)))
+
+
 @dataclass
 class SolveStats:
     iters: int
@@ -169,8 +176,8 @@ def cg_solve(gauge: Gauge, mass: float, b: torch.Tensor, tol: float = 1e-8, inne
     lat = gauge.lat
     _check_c128(b, (lat.Vh, 3), "b")
     inner_p = _prec(inner)
-    if inner_p != L.SP_F64 and inner_p != gauge.lo_prec:
-        raise ValueError("the gauge field's low-precision packing must match the inner precision")
+    if not _links_serve(gauge, inner_p):
+        raise ValueError("the gauge field's low-precision packing cannot serve the inner precision")
     if out is not None:
         _check_c128(out, (lat.Vh, 3), "out")
     x = out if out is not None else torch.empty_like(b)
@@ -206,8 +213,8 @@ def cg_solve_batched(systems, tol: float = 1e-8, inner="f32", max_iter: int = 10
     xs = []
     for i, (gauge, mass, b) in enumerate(systems):
         _check_c128(b, (gauge.lat.Vh, 3), f"b[{i}]")
-        if inner_p != L.SP_F64 and inner_p != gauge.lo_prec:
-            raise ValueError("every gauge field's low-precision packing must match the inner precision")
+        if not _links_serve(gauge, inner_p):
+            raise ValueError("a gauge field's low-precision packing cannot serve the inner precision")
         x = torch.empty_like(b)
         xs.append(x)
         arr[i] = L.sp_system(ctypes.pointer(gauge.lat.geom), ctypes.pointer(gauge.struct), float(mass),
@@ -234,8 +241,8 @@ def full_solve(gauge: Gauge, mass: float, src: torch.Tensor, tol: float = 1e-8, 
     lat = gauge.lat
     _check_c128(src, (lat.V, 3), "src")
     inner_p = _prec(inner)
-    if inner_p != L.SP_F64 and inner_p != gauge.lo_prec:
-        raise ValueError("the gauge field's low-precision packing must match the inner precision")
+    if not _links_serve(gauge, inner_p):
+        raise ValueError("the gauge field's low-precision packing cannot serve the inner precision")
     prm = _params(tol, max_iter, inner_p, delta, ru_every, poll_chunk, 0, use_graph)
     lib = L.load()
     nbytes = lib.sp_full_workspace_bytes(ctypes.byref(lat.geom), ctypes.byref(gauge.struct), ctypes.byref(prm))
@@ -331,6 +338,106 @@ def npr_contract(lat: Lattice, uad: torch.Tensor, chib1, chi2, chib3, chi4, labe
                                      _ptr(chi4), lab, _ptr(out), _stream()), "sp_npr_contract")
     return out
 
+
+class Shard:
+    """One GPU's share of a lattice cut in time (sp_shard): local extents (X, Y, Z, Tl), the global time of its
+    first slice t0 and the global time extent T; bc_t is the global time boundary. Vectors of a shard are
+    extended (ghost slices t0 - 1 and t0 + Tl around the local ones); faces are one slice of one parity."""
+
+    def __init__(self, local_dims, t0: int, T: int, bc_t: int = 0):
+        self.lat = Lattice(local_dims, bc_t)
+        self.t0, self.T = int(t0), int(T)
+        self.struct = L.sp_shard(self.lat.geom, self.t0, self.T)
+        self.F = self.lat.dims[0] * self.lat.dims[1] * self.lat.dims[2] // 2
+
+    def face_bytes(self, prec) -> int:
+        return int(L.load().sp_shard_face_bytes(ctypes.byref(self.struct), _prec(prec)))
+
+    def vec_bytes(self, prec) -> int:
+        return int(L.load().sp_shard_vec_bytes(ctypes.byref(self.struct), _prec(prec)))
+
+    def ghost_bytes(self, prec, recon) -> int:
+        return int(L.load().sp_shard_ghost_bytes(ctypes.byref(self.struct), _prec(prec), int(recon)))
+
+    def pack_vec(self, v: torch.Tensor, prec, ext: torch.Tensor | None = None) -> torch.Tensor:
+        """Local natural half vector [Vh][3] -> an extended vector (a new one, ghosts unset, or ext)."""
+        _check_c128(v, (self.lat.Vh, 3), "vector")
+        nbytes = self.vec_bytes(prec)
+        if ext is None:
+            ext = torch.zeros(nbytes, dtype=torch.uint8, device=v.device)
+        _check_packed(ext, nbytes, "ext")
+        L.check(L.load().sp_shard_vec_pack(ctypes.byref(self.struct), _ptr(v), _prec(prec), _ptr(ext), _stream()),
+                "sp_shard_vec_pack")
+        return ext
+
+    def face_pack(self, prec, ext: torch.Tensor, side: int, face: torch.Tensor | None = None) -> torch.Tensor:
+        _check_packed(ext, self.vec_bytes(prec), "ext")
+        nbytes = self.face_bytes(prec)
+        if face is None:
+            face = torch.empty(nbytes, dtype=torch.uint8, device=ext.device)
+        _check_packed(face, nbytes, "face")
+        L.check(L.load().sp_face_pack(ctypes.byref(self.struct), _prec(prec), _ptr(ext), int(side), _ptr(face),
+                                      _stream()), "sp_face_pack")
+        return face
+
+    def face_unpack(self, prec, face: torch.Tensor, side: int, ext: torch.Tensor) -> torch.Tensor:
+        _check_packed(face, self.face_bytes(prec), "face")
+        _check_packed(ext, self.vec_bytes(prec), "ext")
+        L.check(L.load().sp_face_unpack(ctypes.byref(self.struct), _prec(prec), _ptr(face), int(side), _ptr(ext),
+                                        _stream()), "sp_face_unpack")
+        return ext
+
+    def ghost_pack(self, tlinks: torch.Tensor, prec, recon: int) -> torch.Tensor:
+        """U_t on global slice t0 - 1, complex128 [X Y Z][3][3] -> packed ghost links."""
+        _check_c128(tlinks, (2 * self.F, 3, 3), "tlinks")
+        nbytes = self.ghost_bytes(prec, recon)
+        if nbytes == 0:
+            raise ValueError(f"unsupported packing prec={prec} recon={recon}")
+        out = torch.empty(nbytes, dtype=torch.uint8, device=tlinks.device)
+        L.check(L.load().sp_shard_ghost_pack(ctypes.byref(self.struct), _ptr(tlinks), _prec(prec), int(recon),
+                                             _ptr(out), _stream()), "sp_shard_ghost_pack")
+        return out
+
+    def dslash(self, gauge: Gauge, ghost: torch.Tensor, prec, ext: torch.Tensor, out_parity: int, part: int = 0,
+               out: torch.Tensor | None = None) -> torch.Tensor:
+        """Halo-fed half operator (sp_dslash_halo) into a local packed vector; part 0 all, 1 interior, 2 boundary."""
+        lat = self.lat
+        if gauge.lat.dims != lat.dims:
+            raise ValueError("the gauge field must be packed on the shard's local geometry")
+        _check_packed(ext, self.vec_bytes(prec), "ext", gauge.f64.device)
+        nbytes = lat.vec_bytes(prec)
+        if out is None:
+            out = torch.empty(nbytes, dtype=torch.uint8, device=ext.device)
+        _check_packed(out, nbytes, "out", gauge.f64.device)
+        lp = L.SP_F64 if _prec(prec) == L.SP_F64 else gauge.lo_prec
+        rc = 18 if _prec(prec) == L.SP_F64 else gauge.recon
+        _check_packed(ghost, self.ghost_bytes(lp, rc), "ghost", gauge.f64.device)
+        L.check(L.load().sp_dslash_halo(ctypes.byref(self.struct), ctypes.byref(gauge.struct), _ptr(ghost), _prec(prec),
+                                        _ptr(ext), _ptr(out), int(out_parity), int(part), _stream()), "sp_dslash_halo")
+        return out
+
+STREAM_KINDS = {"read": 0, "copy": 1, "triad": 2}
+
+
+def stream_probe(kind: str, k: int, a: torch.Tensor, b: torch.Tensor, c: torch.Tensor | None = None) -> None:
+    """One launch of the library's streaming-bandwidth probe (sp_stream_probe) over a's 16-byte words: "read"
+    (b receives one float per block, sp_stream_out_bytes), "copy" (b = a) or "triad" (b = a + 0.5 c), k words
+    per lane. Asynchronous on the current stream."""
+    for name, t in (("a", a), ("b", b), ("c", c)):
+        if t is None:
+            continue
+        if not isinstance(t, torch.Tensor) or not t.is_cuda or not t.is_contiguous():
+            raise TypeError(f"{name} must be a contiguous GPU tensor")
+    n16 = a.numel() * a.element_size() // 16
+    lib = L.load()
+    kd = STREAM_KINDS[kind]
+    need = lib.sp_stream_out_bytes(n16, int(k)) if kd == 0 else n16 * 16
+    if b.numel() * b.element_size() < need or (c is not None and c.numel() * c.element_size() < n16 * 16):
+        raise ValueError("output or second input too small for the probe")
+    if kd == 2 and c is None:
+        raise ValueError("triad needs c")
+    L.check(lib.sp_stream_probe(kd, int(k), _ptr(a), _ptr(b), _ptr(c) if c is not None else None,
+                                ctypes.c_size_t(n16), _stream()), "sp_stream_probe")
 
 def tune_dslash(gauge: Gauge, prec) -> float:
     """Pick the fastest launch shape of the half operator for this lattice and precision (ms per call)."""

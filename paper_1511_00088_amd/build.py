@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libstagcg.so")
-SOURCES = ["sp_launch_dslash.hip", "sp_launch_blas.hip", "sp_force.hip", "sp_full.hip", "sp_hyp.hip", "sp_npr.hip", "sp_api.hip", "sp_noalloc.hip"]
+SOURCES = ["sp_launch_dslash.hip", "sp_launch_blas.hip", "sp_force.hip", "sp_full.hip", "sp_hyp.hip", "sp_npr.hip", "sp_api.hip", "sp_noalloc.hip", "sp_stream.hip", "sp_halo.hip"]
 ARCH = os.environ.get("SP_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -66,6 +66,9 @@ int fail(int code, const char* fmt, ...) {
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 bool valid_prec(int p) { return p >= SP_F64 && p <= SP_BF16; }
+// link storage also admits 16-bit fixed point
+bool valid_link_prec(int p) { return valid_prec(p) || p == SP_I16; }
+bool is_16bit_link(int p) { return p == SP_F16 || p == SP_BF16 || p == SP_I16; }
 
 int check_geom(const sp_geom* g, Geom* out) {
     if (!g) return fail(SP_ERR_INVALID_ARG, "geometry is null");
@@ -95,7 +98,8 @@ int check_geom(const sp_geom* g, Geom* out) {
 size_t link_bytes(int prec, int recon) {
     if (prec == SP_F64) return recon == 18 ? 144 : 0;
     if (prec == SP_F32) return recon == 18 ? 72 : recon == 12 ? 48 : 0;
-    return recon == 18 ? 36 : recon == 12 ? 24 : 0;
+    if (prec == SP_F16 || prec == SP_BF16 || prec == SP_I16) return recon == 18 ? 36 : recon == 12 ? 24 : 0;
+    return 0;
 }
 
 size_t vec_site_bytes(int prec) {
@@ -294,8 +298,11 @@ int check_gauge(const sp_gauge* U, int inner) {
     if (!U->f64) return fail(SP_ERR_INVALID_ARG, "gauge f64 packing is null");
     if (inner == SP_F64) return SP_OK;
     if (!U->lo) return fail(SP_ERR_INVALID_ARG, "gauge lo packing is null");
-    if (U->lo_prec != inner)
-        return fail(SP_ERR_UNSUPPORTED, "gauge lo precision %d differs from the inner precision %d", U->lo_prec, inner);
+    // FP32 iterations also take links stored at 16 bits (FP32 vectors and arithmetic); 16-bit vector storage
+    // needs links of its own precision
+    const bool links_ok = U->lo_prec == inner || (inner == SP_F32 && is_16bit_link(U->lo_prec));
+    if (!links_ok)
+        return fail(SP_ERR_UNSUPPORTED, "gauge lo precision %d cannot serve inner precision %d", U->lo_prec, inner);
     if (U->recon != 18 && U->recon != 12) return fail(SP_ERR_INVALID_ARG, "recon must be 18 or 12");
     return SP_OK;
 }
@@ -308,7 +315,7 @@ struct Plan {
     LaunchCfg cfg;
 };
 
-// One system with at most four partials per thread: every block of the update forms alpha itself and
+// One system with at most FUSED_PARTIALS partials per thread: every block of the update forms alpha itself and
 // every block of the launch that updates p forms beta and the stopping decisions itself, so no finalize
 // launch is needed (FP32/FP64: k_norm_rec, k_dslash DS_UPDATE_FUSED; 16-bit: k_dslash DS_NORM,
 // DS_UPDATE_FUSED, k_xpay_fused).
@@ -493,7 +500,11 @@ SolverState initial_state(const sp_system& s, const sp_cg_params* prm) {
     if (prm->inner == SP_F64) every = INT_MAX;
     else if (every <= 0) every = 100;
     st.ru_every = every;
-    st.restart = (prm->inner == SP_F16 || prm->inner == SP_BF16) ? 1 : 0;
+    // 16-bit storage of the vectors or of the links restarts the direction at every reliable update: the
+    // rounded links move the inner operator by about 2^-11 |A| (FP16), far more than the smallest eigenvalue
+    // m^2 of a light-quark system, and a direction kept across an update then stalls the solve
+    const bool links16 = prm->inner == SP_F32 && s.U && is_16bit_link(s.U->lo_prec);
+    st.restart = (prm->inner == SP_F16 || prm->inner == SP_BF16 || links16) ? 1 : 0;
     return st;
 }
 
@@ -708,6 +719,13 @@ namespace sp {
 
 int set_error(int code, const char* msg) { return fail(code, "%s", msg); }
 
+int geom_check(const sp_geom* g, Geom* G) { return check_geom(g, G); }
+
+LaunchCfg tuned_launch(const Geom& G, int lp, int recon, int vp) {
+    std::lock_guard<std::mutex> lock(g_mu);
+    return tuned_cfg(G, lp, recon, vp);
+}
+
 // Argument checks shared by sp_cg_force and its allocation-free variant.
 int force_check(const sp_geom* g, const sp_gauge* U, double mass, const double* x_e, const double* lambda_e,
                 const double* gamma, Geom* G) {
@@ -774,7 +792,7 @@ const char* sp_last_error(void) { return g_last_error.c_str(); }
 
 size_t sp_gauge_bytes(const sp_geom* g, int prec, int recon) {
     Geom G;
-    if (check_geom(g, &G) || !valid_prec(prec)) return 0;
+    if (check_geom(g, &G) || !valid_link_prec(prec)) return 0;
     return 8 * (size_t)G.Vh * link_bytes(prec, recon);
 }
 
@@ -782,7 +800,7 @@ int sp_gauge_pack(const sp_geom* g, const double* links_nat, int prec, int recon
     Geom G;
     int rc = check_geom(g, &G);
     if (rc) return rc;
-    if (!valid_prec(prec)) return fail(SP_ERR_INVALID_ARG, "bad precision %d", prec);
+    if (!valid_link_prec(prec)) return fail(SP_ERR_INVALID_ARG, "bad precision %d", prec);
     if (link_bytes(prec, recon) == 0) return fail(SP_ERR_UNSUPPORTED, "precision %d with recon %d", prec, recon);
     if (!links_nat || !out) return fail(SP_ERR_INVALID_ARG, "null pointer");
     HIP_TRY(launch_pack_gauge(G, links_nat, prec, recon, out, (hipStream_t)stream));
@@ -829,10 +847,11 @@ static int dslash_desc(const sp_geom* g, const sp_gauge* U, int prec, const void
         *lp = SP_F64;
         *recon = 18;
     } else {
-        if (U->lo_prec != prec) return fail(SP_ERR_UNSUPPORTED, "gauge lo precision %d != %d", U->lo_prec, prec);
+        const bool links_ok = U->lo_prec == prec || (prec == SP_F32 && is_16bit_link(U->lo_prec));
+        if (!links_ok) return fail(SP_ERR_UNSUPPORTED, "gauge lo precision %d with vectors of precision %d", U->lo_prec, prec);
         if (U->recon != 18 && U->recon != 12) return fail(SP_ERR_INVALID_ARG, "recon must be 18 or 12");
         links = U->lo;
-        *lp = prec;
+        *lp = U->lo_prec;
         *recon = U->recon;
     }
     if (!links) return fail(SP_ERR_INVALID_ARG, "gauge field of precision %d is null", prec);
@@ -883,32 +902,40 @@ int sp_tune_dslash(const sp_geom* g, const sp_gauge* U, int prec, void* in, void
     HIP_TRY(hipEventCreate(&ev.b));
     hipEvent_t e0 = ev.a, e1 = ev.b;
     const int nts[3] = {64, 128, 256};
-    const int reps = 20;
+    const int reps = 10, trials = 5;
     const int use64 = prec == SP_F64;
-    // mean time of `reps` launches after 3 warm-ups, for every block size and block order; the fastest wins
-    auto sweep = [&](auto launch, LaunchCfg* best, float* best_t) -> hipError_t {
+    // For every block size, block order and (for the one-right-hand-side operator) link-load policy: 3 warm-up
+    // launches, then `trials` timings of `reps` back-to-back launches; the median trial's time per launch
+    // counts and the fastest configuration wins. Back-to-back launches are the solver's situation (a link field
+    // that fits in the Infinity Cache stays there between the iteration's launches).
+    auto sweep = [&](auto launch, bool policies, LaunchCfg* best, float* best_t) -> hipError_t {
         *best_t = 1e30f;
-        for (int remap = 0; remap <= 1; ++remap)
-            for (int nt : nts) {
-                LaunchCfg c;
-                c.nt = nt;
-                c.remap = remap;
-                hipError_t e;
-                for (int w = 0; w < 3; ++w)
-                    if ((e = launch(c))) return e;
-                if ((e = hipEventRecord(e0, s))) return e;
-                for (int r = 0; r < reps; ++r)
-                    if ((e = launch(c))) return e;
-                if ((e = hipEventRecord(e1, s))) return e;
-                if ((e = hipEventSynchronize(e1))) return e;
-                float ms = 0;
-                if ((e = hipEventElapsedTime(&ms, e0, e1))) return e;
-                ms /= reps;
-                if (ms < *best_t) {
-                    *best_t = ms;
-                    *best = c;
+        for (int stream_links = 0; stream_links <= (policies ? 1 : 0); ++stream_links)
+            for (int remap = 0; remap <= 1; ++remap)
+                for (int nt : nts) {
+                    LaunchCfg c;
+                    c.nt = nt;
+                    c.remap = remap;
+                    c.stream = stream_links;
+                    hipError_t e;
+                    for (int w = 0; w < 3; ++w)
+                        if ((e = launch(c))) return e;
+                    float t[trials];
+                    for (int k = 0; k < trials; ++k) {
+                        if ((e = hipEventRecord(e0, s))) return e;
+                        for (int r = 0; r < reps; ++r)
+                            if ((e = launch(c))) return e;
+                        if ((e = hipEventRecord(e1, s))) return e;
+                        if ((e = hipEventSynchronize(e1))) return e;
+                        if ((e = hipEventElapsedTime(&t[k], e0, e1))) return e;
+                    }
+                    std::sort(t, t + trials);
+                    const float ms = t[trials / 2] / reps;
+                    if (ms < *best_t) {
+                        *best_t = ms;
+                        *best = c;
+                    }
                 }
-            }
         return hipSuccess;
     };
     LaunchCfg best, best4;
@@ -919,7 +946,7 @@ int sp_tune_dslash(const sp_geom* g, const sp_gauge* U, int prec, void* in, void
             d.grp.nblk = nb;
             return launch_dslash(d, nb, c, lp, recon, prec, 1, S_P, S_T, DS_PLAIN, G_NONE, use64, s);
         },
-        &best, &best_t));
+        true, &best, &best_t));
     // The NB-right-hand-side operator of batched solves has its own register use and therefore its own
     // best shape (key suffix "/n4"). It is timed on NB copies of the input into NB outputs, in a temporary
     // device buffer that also holds the group and system descriptors; the buffer is freed before return.
@@ -959,7 +986,7 @@ int sp_tune_dslash(const sp_geom* g, const sp_gauge* U, int prec, void* in, void
                     }
                     return launch_dslash(db, nb, c, lp, recon, prec, 1, S_P, S_T, DS_PLAIN, G_NONE, use64, s);
                 },
-                &best4, &best4_t);
+                false, &best4, &best4_t);
         const hipError_t es = hipStreamSynchronize(s);
         (void)hipFree(buf);
         HIP_TRY(e);
@@ -982,8 +1009,8 @@ int sp_tune_save(const char* path) {
     f << "{\n";
     size_t i = 0;
     for (auto& kv : g_tune) {
-        f << "  \"" << kv.first << "\": {\"nt\": " << kv.second.nt << ", \"remap\": " << kv.second.remap << "}"
-          << (++i < g_tune.size() ? ",\n" : "\n");
+        f << "  \"" << kv.first << "\": {\"nt\": " << kv.second.nt << ", \"remap\": " << kv.second.remap
+          << ", \"stream\": " << kv.second.stream << "}" << (++i < g_tune.size() ? ",\n" : "\n");
     }
     f << "}\n";
     return SP_OK;
@@ -1001,19 +1028,29 @@ int sp_tune_load(const char* path) {
     size_t pos = 0;
     while ((pos = txt.find('"', pos)) != std::string::npos) {
         const size_t end = txt.find('"', pos + 1);
-        if (end == std::string::npos) break;
+        if (end == std::string::npos) return fail(SP_ERR_INVALID_ARG, "unterminated key in %s", path);
         const std::string key = txt.substr(pos + 1, end - pos - 1);
         LaunchCfg c;
-        int nt = 0, remap = 0;
+        int nt = 0, remap = 0, stream_links = 0;
         const size_t brace = txt.find('{', end);
-        if (brace == std::string::npos) break;
+        if (brace == std::string::npos) return fail(SP_ERR_INVALID_ARG, "tuning key %s has no entry", key.c_str());
         const size_t close = txt.find('}', brace);
-        if (close == std::string::npos ||
-            sscanf(txt.c_str() + brace, "{\"nt\": %d, \"remap\": %d}", &nt, &remap) != 2)
-            return fail(SP_ERR_INVALID_ARG, "malformed tuning entry for %s", key.c_str());
+        if (close == std::string::npos) return fail(SP_ERR_INVALID_ARG, "malformed tuning entry for %s", key.c_str());
+        const std::string entry = txt.substr(brace, close - brace + 1);
+        // {"nt": N, "remap": R, "stream": S}; tables written before the link-load policy existed omit "stream"
+        // the whole entry must match one of the two forms (%n: characters consumed up to the closing brace)
+        int used3 = -1, used2 = -1;
+        sscanf(entry.c_str(), "{\"nt\": %d, \"remap\": %d, \"stream\": %d}%n", &nt, &remap, &stream_links, &used3);
+        if (used3 != (int)entry.size()) {
+            stream_links = 0;
+            sscanf(entry.c_str(), "{\"nt\": %d, \"remap\": %d}%n", &nt, &remap, &used2);
+            if (used2 != (int)entry.size())
+                return fail(SP_ERR_INVALID_ARG, "malformed tuning entry for %s", key.c_str());
+        }
         if (nt != 64 && nt != 128 && nt != 256) return fail(SP_ERR_INVALID_ARG, "bad block size %d", nt);
         c.nt = nt;
         c.remap = remap ? 1 : 0;
+        c.stream = stream_links ? 1 : 0;
         parsed[key] = c;
         pos = close + 1;
     }

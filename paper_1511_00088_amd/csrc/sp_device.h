@@ -8,7 +8,8 @@
 
 namespace sp {
 
-enum Prec : int { F64 = 0, F32 = 1, F16 = 2, BF16 = 3 };
+// I16: 16-bit fixed point q / 32767 (link storage only: SU(3) entries lie in [-1, 1])
+enum Prec : int { F64 = 0, F32 = 1, F16 = 2, BF16 = 3, I16 = 4 };
 
 // ------------------------------------------------------------------------------------------------------
 // Complex colour vectors and 3x3 links
@@ -101,21 +102,36 @@ __device__ __forceinline__ float f16_bits_to_f32(uint32_t b) {
     return (float)__builtin_bit_cast(_Float16, (uint16_t)(b & 0xffffu));
 }
 
+// 16-bit fixed point: q = round(32767 v) clamped to [-32767, 32767]; the absolute error is at most 2^-16 for
+// every |v| <= 1, where FP16 keeps a relative 2^-11 (an error of 2^-12 near 1, the size of smeared links'
+// diagonal entries)
+__device__ __forceinline__ uint32_t f32_to_i16_bits(float f) {
+    const float q = fminf(fmaxf(rintf(f * 32767.0f), -32767.0f), 32767.0f);
+    return (uint32_t)(uint16_t)(int16_t)q;
+}
+__device__ __forceinline__ float i16_bits_to_f32(uint32_t b) {
+    return (float)(int16_t)(uint16_t)(b & 0xffffu) * (1.0f / 32767.0f);
+}
+
 template <int P>
 __device__ __forceinline__ uint32_t pack2(float a, float b) {
     if constexpr (P == F16)
         return f32_to_f16_bits(a) | (f32_to_f16_bits(b) << 16);
+    else if constexpr (P == I16)
+        return f32_to_i16_bits(a) | (f32_to_i16_bits(b) << 16);
     else
         return f32_to_bf16_bits(a) | (f32_to_bf16_bits(b) << 16);
 }
 template <int P>
 __device__ __forceinline__ float unpack_lo(uint32_t w) {
     if constexpr (P == F16) return f16_bits_to_f32(w);
+    else if constexpr (P == I16) return i16_bits_to_f32(w);
     else return bf16_bits_to_f32(w & 0xffffu);
 }
 template <int P>
 __device__ __forceinline__ float unpack_hi(uint32_t w) {
     if constexpr (P == F16) return f16_bits_to_f32(w >> 16);
+    else if constexpr (P == I16) return i16_bits_to_f32(w >> 16);
     else return bf16_bits_to_f32(w >> 16);
 }
 
@@ -250,6 +266,69 @@ template <>
 struct VecFmt<BF16> : VecFmt16<BF16> {};
 
 // ------------------------------------------------------------------------------------------------------
+// Loads of packed link words. NT = false: ordinary cached loads. NT = true: non-temporal (streaming) loads,
+// which mark the lines for early eviction: a link field read once per launch then does not push the
+// neighbour vectors (each read by eight sites) out of the caches. Cached loads keep a link field that fits
+// in the Infinity Cache there between launches; which one is faster depends on the lattice size, and the
+// launch autotuner chooses.
+// ------------------------------------------------------------------------------------------------------
+template <bool NT>
+__device__ __forceinline__ float4 ldw(const float4* p) {
+    if constexpr (NT) {
+        typedef float v4 __attribute__((ext_vector_type(4)));
+        const v4 v = __builtin_nontemporal_load((const v4*)p);
+        return make_float4(v.x, v.y, v.z, v.w);
+    } else {
+        return *p;
+    }
+}
+template <bool NT>
+__device__ __forceinline__ float2 ldw(const float2* p) {
+    if constexpr (NT) {
+        typedef float v2 __attribute__((ext_vector_type(2)));
+        const v2 v = __builtin_nontemporal_load((const v2*)p);
+        return make_float2(v.x, v.y);
+    } else {
+        return *p;
+    }
+}
+template <bool NT>
+__device__ __forceinline__ double2 ldw(const double2* p) {
+    if constexpr (NT) {
+        typedef double v2 __attribute__((ext_vector_type(2)));
+        const v2 v = __builtin_nontemporal_load((const v2*)p);
+        return make_double2(v.x, v.y);
+    } else {
+        return *p;
+    }
+}
+template <bool NT>
+__device__ __forceinline__ uint4 ldw(const uint4* p) {
+    if constexpr (NT) {
+        typedef unsigned int v4 __attribute__((ext_vector_type(4)));
+        const v4 v = __builtin_nontemporal_load((const v4*)p);
+        return make_uint4(v.x, v.y, v.z, v.w);
+    } else {
+        return *p;
+    }
+}
+template <bool NT>
+__device__ __forceinline__ uint2 ldw(const uint2* p) {
+    if constexpr (NT) {
+        typedef unsigned int v2 __attribute__((ext_vector_type(2)));
+        const v2 v = __builtin_nontemporal_load((const v2*)p);
+        return make_uint2(v.x, v.y);
+    } else {
+        return *p;
+    }
+}
+template <bool NT>
+__device__ __forceinline__ uint32_t ldw(const uint32_t* p) {
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+
+// ------------------------------------------------------------------------------------------------------
 // Link storage. The packed field is 8 blocks (parity q = 0,1) x (mu = 0..3), block (q, mu) holding
 // U_mu(n) for the Vh sites n of parity q in cb order, as planes:
 //   F64  r18: 9 planes double2                         144 B/link
@@ -265,12 +344,13 @@ struct LinkFmt;
 template <>
 struct LinkFmt<F64, 18> {
     static constexpr int bytes = 144;
+    template <bool NT = false>
     __device__ static Su3<double> load(const void* blk, int Vh, int cb) {
         const double2* p = (const double2*)blk;
         Su3<double> U;
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
-            double2 a = p[(size_t)k * Vh + cb];
+            double2 a = ldw<NT>(p + (size_t)k * Vh + cb);
             U.e[k / 3][k % 3].re = a.x;
             U.e[k / 3][k % 3].im = a.y;
         }
@@ -287,16 +367,17 @@ template <int RECON>
 struct LinkFmtF32 {
     static constexpr int nq = RECON == 18 ? 4 : 3;  // float4 planes
     static constexpr int bytes = RECON == 18 ? 72 : 48;
+    template <bool NT = false>
     __device__ static Su3<float> load(const void* blk, int Vh, int cb) {
         const float4* p = (const float4*)blk;
         float f[18];
 #pragma unroll
         for (int k = 0; k < nq; ++k) {
-            float4 a = p[(size_t)k * Vh + cb];
+            float4 a = ldw<NT>(p + (size_t)k * Vh + cb);
             f[4 * k] = a.x; f[4 * k + 1] = a.y; f[4 * k + 2] = a.z; f[4 * k + 3] = a.w;
         }
         if constexpr (RECON == 18) {
-            float2 b = ((const float2*)(p + (size_t)4 * Vh))[cb];
+            float2 b = ldw<NT>((const float2*)(p + (size_t)4 * Vh) + cb);
             f[16] = b.x; f[17] = b.y;
         }
         Su3<float> U;
@@ -324,17 +405,18 @@ struct LinkFmt<F32, 12> : LinkFmtF32<12> {};
 template <int P, int RECON>
 struct LinkFmt16 {
     static constexpr int bytes = RECON == 18 ? 36 : 24;
+    template <bool NT = false>
     __device__ static Su3<float> load(const void* blk, int Vh, int cb) {
         const uint4* p = (const uint4*)blk;
         uint32_t w[9];
-        uint4 a = p[cb];
+        uint4 a = ldw<NT>(p + cb);
         w[0] = a.x; w[1] = a.y; w[2] = a.z; w[3] = a.w;
         if constexpr (RECON == 18) {
-            uint4 b = p[(size_t)Vh + cb];
+            uint4 b = ldw<NT>(p + (size_t)Vh + cb);
             w[4] = b.x; w[5] = b.y; w[6] = b.z; w[7] = b.w;
-            w[8] = ((const uint32_t*)(p + (size_t)2 * Vh))[cb];
+            w[8] = ldw<NT>((const uint32_t*)(p + (size_t)2 * Vh) + cb);
         } else {
-            uint2 b = ((const uint2*)(p + (size_t)Vh))[cb];
+            uint2 b = ldw<NT>((const uint2*)(p + (size_t)Vh) + cb);
             w[4] = b.x; w[5] = b.y;
         }
         Su3<float> U;
@@ -368,6 +450,10 @@ template <>
 struct LinkFmt<BF16, 18> : LinkFmt16<BF16, 18> {};
 template <>
 struct LinkFmt<BF16, 12> : LinkFmt16<BF16, 12> {};
+template <>
+struct LinkFmt<I16, 18> : LinkFmt16<I16, 18> {};
+template <>
+struct LinkFmt<I16, 12> : LinkFmt16<I16, 12> {};
 
 // Address of block (q, mu) of a packed gauge field.
 template <class LF>
@@ -440,14 +526,14 @@ __host__ __device__ __forceinline__ float eta_sign(const Site& s, int mu) {
 // with s_f, s_b the antiperiodic-time signs of the two links. Links of parity p are the forward links;
 // the backward link U_mu(n-mu) sits at the neighbour's cb in the parity 1-p block.
 // ------------------------------------------------------------------------------------------------------
-template <int LP, int RECON, int VP>
+template <int LP, int RECON, int VP, bool NT = false>
 __device__ __forceinline__ Vec3<typename Real<VP>::T> dslash_site(const Geom g, const void* links, const void* in,
                                                                   int p, const Site s) {
     using R = typename Real<VP>::T;
     using LF = LinkFmt<LP, RECON>;
     using VF = VecFmt<VP>;
     Vec3<R> acc = vzero<R>();
-    constexpr int UNROLL = (VP == F64 || (LP == F32 && RECON == 12)) ? 2 : 4;
+    constexpr int UNROLL = (VP == F64 || (LP == F32 && RECON == 12 && !NT)) ? 2 : 4;
 #pragma unroll UNROLL
     for (int mu = 0; mu < 4; ++mu) {
         R e = (R)eta_sign(s, mu);
@@ -458,9 +544,9 @@ __device__ __forceinline__ Vec3<typename Real<VP>::T> dslash_site(const Geom g, 
         }
         int nf = nbr(g, s, mu, +1);
         int nb = nbr(g, s, mu, -1);
-        Su3<R> Uf = LF::load(link_block<LF>(links, g.Vh, p, mu), g.Vh, s.cb);
+        Su3<R> Uf = LF::template load<NT>(link_block<LF>(links, g.Vh, p, mu), g.Vh, s.cb);
         Vec3<R> vf = VF::load(in, g.Vh, nf);
-        Su3<R> Ub = LF::load(link_block<LF>(links, g.Vh, 1 - p, mu), g.Vh, nb);
+        Su3<R> Ub = LF::template load<NT>(link_block<LF>(links, g.Vh, 1 - p, mu), g.Vh, nb);
         Vec3<R> vb = VF::load(in, g.Vh, nb);
         mv_acc(acc, Uf, vf, sf);
         mdv_acc(acc, Ub, vb, -sb);

@@ -10,6 +10,12 @@ namespace sp {
 // Records msg as the calling thread's last error (sp_last_error) and returns code.
 int set_error(int code, const char* msg);
 
+// Validates an sp_geom (even extents >= 2, V/2 < 2^24, bc_t 0 or 1) and fills G; returns an sp_status.
+int geom_check(const sp_geom* g, Geom* G);
+
+// The tuned launch shape of the half operator for (G, link precision, recon, vector precision), or the default.
+LaunchCfg tuned_launch(const Geom& G, int lp, int recon, int vp);
+
 // Checks of sp_cg_force's arguments (geometry, null pointers, finite mass); fills G.
 int force_check(const sp_geom* g, const sp_gauge* U, double mass, const double* x_e, const double* lambda_e,
                 const double* gamma, Geom* G);

@@ -158,7 +158,7 @@ enum DsMode : int { DS_PLAIN = 0, DS_NORM = 1, DS_UPDATE = 2, DS_UPDATE_FUSED = 
 // right-hand sides beyond the group's count read the last system's vectors and store nothing, and systems
 // that are stopped or paused are computed with zero coefficients (x += 0 p, r -= 0 q, p = 0 r + 1 p leave
 // their stored values unchanged). Only temporaries (t) are overwritten for them.
-template <int LP, int RECON, int VP, int N, class D, int MODE>
+template <int LP, int RECON, int VP, int N, class D, int MODE, bool NT = false>
 __global__ __launch_bounds__(256) void k_dslash(D d, int p, int in_slot, int out_slot, int gate, int use64,
                                                 int remap) {
     using R = typename Real<VP>::T;
@@ -202,7 +202,7 @@ __global__ __launch_bounds__(256) void k_dslash(D d, int p, int in_slot, int out
 // one direction at a time for several systems (their gathers would not fit in registers otherwise); two at
 // a time in FP64, where all four put 384 values in flight and leave one wave per SIMD, and for FP32
 // recon-12, whose row rebuild makes four at a time cost 125-136 VGPRs (measured 3-4% slower)
-        constexpr int UNROLL = N == 1 ? ((VP == F64 || (LP == F32 && RECON == 12)) ? 2 : 4) : 1;
+        constexpr int UNROLL = N == 1 ? ((VP == F64 || (LP == F32 && RECON == 12 && !NT)) ? 2 : 4) : 1;
 #pragma unroll UNROLL
         for (int mu = 0; mu < 4; ++mu) {
             R e = (R)eta_sign(s, mu);
@@ -213,13 +213,13 @@ __global__ __launch_bounds__(256) void k_dslash(D d, int p, int in_slot, int out
             }
             const int nf = nbr(g, s, mu, +1);
             const int nb = nbr(g, s, mu, -1);
-            const Su3<R> Uf = LF::load(link_block<LF>(links, g.Vh, p, mu), g.Vh, cb);
+            const Su3<R> Uf = LF::template load<NT>(link_block<LF>(links, g.Vh, p, mu), g.Vh, cb);
             Vec3<R> v[N];
 #pragma unroll
             for (int r = 0; r < N; ++r) v[r] = VF::load(in[r], g.Vh, nf);
 #pragma unroll
             for (int r = 0; r < N; ++r) mv_acc(acc[r], Uf, v[r], sf);
-            const Su3<R> Ub = LF::load(link_block<LF>(links, g.Vh, 1 - p, mu), g.Vh, nb);
+            const Su3<R> Ub = LF::template load<NT>(link_block<LF>(links, g.Vh, 1 - p, mu), g.Vh, nb);
 #pragma unroll
             for (int r = 0; r < N; ++r) v[r] = VF::load(in[r], g.Vh, nb);
 #pragma unroll
@@ -533,7 +533,7 @@ __global__ __launch_bounds__(256) void k_xpay_fused(DescSingle d, SolverState* _
 // state to st_out. When p was formed elsewhere (start, reliable update, end of the last chunk: ST_T_STALE)
 // the launch applies D_oe to p directly and takes no decision. Partials: Re<D_oe in, t> as DS_NORM, and
 // |p_i|^2 from the recurrence (the other paths leave the |p|^2 partials of the launch that formed p).
-template <int LP, int RECON, int VP>
+template <int LP, int RECON, int VP, bool NT = false>
 __global__ __launch_bounds__(256) void k_norm_rec(DescSingle d, SolverState* __restrict__ st_out, int remap) {
     using R = typename Real<VP>::T;
     using VF = VecFmt<VP>;
@@ -555,7 +555,7 @@ __global__ __launch_bounds__(256) void k_norm_rec(DescSingle d, SolverState* __r
         for (int b = threadIdx.x; b < G.nblk; b += blockDim.x) part[0] += G.partials_r[b];
     Vec3<R> acc = vzero<R>(), told = vzero<R>(), rv = vzero<R>(), pv = vzero<R>();
     if (live) {
-        acc = dslash_site<LP, RECON, VP>(g, G.links_lo, direct ? S.v[S_P] : S.v[S_R], 1, site_of(g, 1, cb));
+        acc = dslash_site<LP, RECON, VP, NT>(g, G.links_lo, direct ? S.v[S_P] : S.v[S_R], 1, site_of(g, 1, cb));
         if (!direct) {
             told = VF::load(S.v[S_T], g.Vh, cb);
             rv = VF::load(S.v[S_R], g.Vh, cb);

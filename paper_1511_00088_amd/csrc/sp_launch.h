@@ -10,6 +10,7 @@ namespace sp {
 struct LaunchCfg {
     int nt = 256;    // threads per block (64, 128 or 256)
     int remap = 1;   // XCD-aware block order
+    int stream = 0;  // link loads of the single-system half operator: 0 cached, 1 streaming (non-temporal)
 };
 
 // Maximum systems per group in batched launches.
@@ -17,8 +18,11 @@ static constexpr int NB = 4;
 
 inline int blocks_for(int n, int nt) { return (n + nt - 1) / nt; }
 
-// The fused single-system iteration has every block sum all block partials: at most this many per thread.
-static constexpr int FUSED_PARTIALS = 4;
+// The fused single-system iteration has every block sum all block partials of the previous launch (in the same
+// order in every block): at most this many per thread. 32 admits 8,192 blocks of 256 threads (V/2 up to 2^21:
+// the 32^3x64 control and the 28^3x96 production lattice). The partials are loaded before the gather, so their
+// latency overlaps the link loads; each block reads them all (8 bytes per block of the launch) from L2.
+static constexpr int FUSED_PARTIALS = 32;
 
 // Half operator (see k_dslash; mode DS_PLAIN, DS_NORM or DS_UPDATE). D = DescSingle (one system) or
 // DescBatch (up to NB per group).

@@ -104,6 +104,8 @@ hipError_t launch_pack_gauge(const Geom& g, const double* nat, int prec, int rec
     if (prec == F16 && recon == 12) SP_LAUNCH(F16, 12);
     if (prec == BF16 && recon == 18) SP_LAUNCH(BF16, 18);
     if (prec == BF16 && recon == 12) SP_LAUNCH(BF16, 12);
+    if (prec == I16 && recon == 18) SP_LAUNCH(I16, 18);
+    if (prec == I16 && recon == 12) SP_LAUNCH(I16, 12);
 #undef SP_LAUNCH
     return hipErrorInvalidValue;
 }
