@@ -40,6 +40,9 @@ def test_host_queries():
     assert lat.gauge_bytes("f32", 12) == 4 * 512000 * 48
     assert lat.gauge_bytes("f16", 12) == 4 * 512000 * 24
     assert lat.gauge_bytes("f64", 12) == 0  # not supported
+    assert lat.gauge_bytes("i16", 12) == 4 * 512000 * 24  # 16-bit fixed-point links
+    assert lat.gauge_bytes("i16", 18) == 4 * 512000 * 36
+    assert lat.vec_bytes("i16") == 0  # links only: no vector storage of that kind
     assert sp.Lattice((4, 4, 5, 4)).vec_bytes("f32") == 0  # odd extent
     assert sp.Lattice((256, 256, 256, 2)).vec_bytes("f32") == 0  # V/2 >= 2^24
 
@@ -138,13 +141,16 @@ def test_geometry_limits_and_degenerate_calls():
 def test_tune_cache_roundtrip(tmp_path):
     lib = _lib.load()
     p = tmp_path / "tune.json"
-    p.write_text('{\n  "20x20x20x64/l1/r18/v1": {"nt": 128, "remap": 1},\n'
+    # the second entry has the form tables took before the link-load policy ("stream") existed: cached loads
+    p.write_text('{\n  "20x20x20x64/l1/r18/v1": {"nt": 128, "remap": 1, "stream": 1},\n'
                  '  "20x20x20x64/l1/r18/v1/n4": {"nt": 256, "remap": 0}\n}\n')
     assert lib.sp_tune_load(str(p).encode()) == 0
     q = tmp_path / "out.json"
     assert lib.sp_tune_save(str(q).encode()) == 0
-    assert '"20x20x20x64/l1/r18/v1": {"nt": 128, "remap": 1}' in q.read_text()
-    assert '"20x20x20x64/l1/r18/v1/n4": {"nt": 256, "remap": 0}' in q.read_text()
+    assert '"20x20x20x64/l1/r18/v1": {"nt": 128, "remap": 1, "stream": 1}' in q.read_text()
+    assert '"20x20x20x64/l1/r18/v1/n4": {"nt": 256, "remap": 0, "stream": 0}' in q.read_text()
+    p.write_text('{"x": {"nt": 128, "remap": 1, "strem": 1}}')
+    assert lib.sp_tune_load(str(p).encode()) == _lib.SP_ERR_INVALID_ARG
     p.write_text('{"x": {"nt": 100, "remap": 1}}')
     assert lib.sp_tune_load(str(p).encode()) == _lib.SP_ERR_INVALID_ARG
     lib.sp_release_cache()

@@ -258,3 +258,47 @@ def test_batched_mixed_packings_rejected():
     with pytest.raises(sp.StagError) as e:
         sp.cg_solve_batched([(G18, 0.1, b), (G12, 0.1, b)], tol=1e-8, inner="f32")
     assert e.value.code == -3
+
+
+def test_batched_workload_32_systems_vs_oracle():
+    """The benchmark's batched workload itself (lattice_inputs.uneven_batch: 8 right-hand sides on the 20^3x64
+    field at m = 0.01, and 8 systems each on 8^4, 12^3x24 and 16^3x32 with masses in [0.01, 0.1]) in the launch the
+    benchmark times (FP32 iterations on recon-12 links, tuned table): every system's true residual recomputed by
+    the oracle's FP64 operator, and each of the 24 smaller systems against the oracle's own 1e-12 solve (run in
+    threads: each is single-threaded and releases the interpreter)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    sp.tune_load(tune_file())
+    gauges, systems = li.uneven_batch()
+    G = [gauge(dims, U, "f32", 12) for dims, U in gauges]
+    sysl = [(G[s.gauge_index], s.mass, to_dev(s.source)) for s in systems]
+    announce(f"batched workload: {len(sysl)} systems, f32 r12")
+    xs, stats = sp.cg_solve_batched(sysl, tol=1e-8, inner="f32")
+    xh = [to_host(x) for x in xs]
+
+    def check(i):
+        s = systems[i]
+        dims, U = gauges[s.gauge_index]
+        res = _true_resid_oracle(dims, U, s.mass, s.source, xh[i])
+        err = None
+        if li.volume(dims) < li.volume((20, 20, 20, 64)):
+            xr, st0, _, _ = oracle.cg_solve(dims, U, s.mass, s.source, tol=1e-12)
+            assert st0 == 0
+            err = rel_err_2(xh[i], xr)
+        return res, err
+
+    with ThreadPoolExecutor(8) as ex:
+        out = list(ex.map(check, range(len(systems))))
+    for i, (s, st, (res, err)) in enumerate(zip(systems, stats, out)):
+        announce(f"  sys {i} dims={s.dims} m={s.mass:.4f}: iters={st.iters} ru={st.reliable_updates} "
+                 f"resid={st.true_rel_resid:.2e} oracle-resid={res:.2e} err={err if err is None else f'{err:.2e}'}")
+        assert st.converged and st.status == 0 and st.true_rel_resid <= 1e-8
+        assert res <= 1.01e-8
+        if err is not None:
+            assert err <= 1e-6
+    assert sum(e is not None for _, e in out) == 24
+
+
+def _true_resid_oracle(dims, U, m, b, x):
+    r = b - oracle.apply_A(dims, U, m, x)
+    return float(np.linalg.norm(r) / np.linalg.norm(b))

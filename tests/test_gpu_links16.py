@@ -1,0 +1,176 @@
+"""GPU parity of the FP32 iterations on links stored in 16 bits (FP16, BF16 or 16-bit fixed point, recon 18 or 12)
+with FP32 vectors and arithmetic, through the C-ABI, against the FP64 oracle.
+
+The half operator carries the links' rounding (unit roundoff 2^-11 for FP16, 2^-8 for BF16), so it is gated like
+the 16-bit storage (5e-3 and 3e-2, infinity-norm relative). The solve reaches the exact system's answer through
+the FP64 reliable updates: within 1e-6 of the oracle's 1e-12 solution at a 1e-8 true residual, as for every other
+inner precision.
+"""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import lattice_inputs as li
+import oracle
+import paper_1511_00088_amd as sp
+from conftest import rel_err_2, rel_err_max
+from gpu_common import announce, cfg1_golden, to_dev, to_host, tune_file
+
+pytestmark = pytest.mark.gpu
+
+LINKS = [("f16", 12), ("f16", 18), ("bf16", 12), ("bf16", 18), ("i16", 12), ("i16", 18)]
+# FP16 and BF16 links: the 16-bit storage gates. 16-bit fixed point: every entry within 2^-16 of the link, so the
+# eight mat-vecs of a site move by at most 8 x 3 x 2^-16 |in|, 3.7e-4 of max|in|; the output's maximum is of the
+# order of max|in|, and the gate is 1e-3
+OP_TOL = {"f16": 5e-3, "bf16": 3e-2, "i16": 1e-3}
+
+
+def gauge16(dims, U, lp, recon, bc_t=0):
+    return sp.Gauge(sp.Lattice(dims, bc_t), to_dev(U), lo_prec=lp, recon=recon)
+
+
+def _true_resid(dims, U, m, b, x, bc_t=0):
+    r = b - oracle.apply_A(dims, U, m, x, bc_t=bc_t)
+    return np.linalg.norm(r) / np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("lp,recon", LINKS)
+@pytest.mark.parametrize("dims,bc_t", [((4, 4, 4, 4), 0), ((8, 6, 4, 10), 1), ((2, 2, 2, 2), 1), ((2, 6, 4, 2), 1)])
+def test_operator_small(lp, recon, dims, bc_t):
+    announce(f"links16 dslash {lp} r{recon} dims={dims} bc_t={bc_t}")
+    V = li.volume(dims)
+    U = li.haar_links(dims, 501) if dims != (8, 6, 4, 10) else li.near_identity_links(dims, 0.3, 502)
+    G = gauge16(dims, U, lp, recon, bc_t)
+    for p in (0, 1):
+        xin = li.gaussian_vector(V // 2, 503 + p)
+        y = to_host(sp.dslash(G, to_dev(xin), p, "f32"))
+        ref = oracle.dslash_eo(dims, U, xin, p, bc_t=bc_t)
+        err = rel_err_max(y, ref)
+        announce(f"  parity {p}: max rel err {err:.3e}")
+        assert err <= OP_TOL[lp]
+
+
+@pytest.mark.parametrize("lp,recon", LINKS)
+def test_operator_workload_sampled(lp, recon):
+    dims = (20, 20, 20, 64)
+    announce(f"links16 dslash 20^3x64 sampled {lp} r{recon}")
+    U = _cfg1()["links"]
+    V = li.volume(dims)
+    G = gauge16(dims, U, lp, recon)
+    sp.tune_load(tune_file())
+    xin = li.gaussian_vector(V // 2, 504)
+    rng = np.random.default_rng(505)
+    cbs = np.unique(np.concatenate([rng.integers(0, V // 2, 3000), np.arange(V // 2 - 300, V // 2), np.arange(300)]))
+    for p in (0, 1):
+        y = to_host(sp.dslash(G, to_dev(xin), p, "f32"))[cbs]
+        err = rel_err_max(y, oracle.dslash_eo_sites(dims, U, xin, p, cbs))
+        announce(f"  parity {p}: sampled max rel err {err:.3e}")
+        assert err <= OP_TOL[lp]
+
+
+SMALL = [((8, 8, 8, 8), 0), ((6, 8, 4, 12), 1), ((2, 4, 6, 8), 1), ((4, 4, 2, 2), 1)]
+
+
+@pytest.mark.parametrize("lp,recon", LINKS)
+@pytest.mark.parametrize("dims,bc_t", SMALL)
+def test_solve_small(lp, recon, dims, bc_t):
+    announce(f"links16 cg {lp} r{recon} dims={dims} bc_t={bc_t}")
+    U = li.near_identity_links(dims, 0.3, 511)
+    b = li.gaussian_even_source(dims, 512)
+    m = 0.02
+    G = gauge16(dims, U, lp, recon, bc_t)
+    x, st = sp.cg_solve(G, m, to_dev(b), tol=1e-8, inner="f32")
+    x = to_host(x)
+    xr, _, it0, _ = oracle.cg_solve(dims, U, m, b, tol=1e-12, bc_t=bc_t)
+    err, res = rel_err_2(x, xr), _true_resid(dims, U, m, b, x, bc_t)
+    announce(f"  iters={st.iters} (oracle {it0}) ru={st.reliable_updates} resid={st.true_rel_resid:.3e} "
+             f"oracle-resid={res:.3e} err={err:.3e}")
+    assert st.converged and st.status == 0
+    assert st.true_rel_resid <= 1e-8 and res <= 1.01e-8
+    assert err <= 1e-6
+
+
+_C = {}
+
+
+def _cfg1():
+    if "c" not in _C:
+        _C["c"] = li.cfg1()
+    return _C["c"]
+
+
+@pytest.mark.parametrize("lp,recon", LINKS)
+def test_solve_workload_vs_oracle_samples(lp, recon):
+    """20^3x64, m = 0.01, to 1e-8 in the benchmark's launch: the solution at the oracle's sampled sites (golden
+    file written by the oracle alone) and the true residual of the whole solution through the oracle's operator."""
+    c = _cfg1()
+    dims, U, m, b = c["dims"], c["links"], c["mass"], c["source"]
+    sp.tune_load(tune_file())
+    announce(f"links16 cg 20^3x64 {lp} r{recon}")
+    G = gauge16(dims, U, lp, recon)
+    x, st = sp.cg_solve(G, m, to_dev(b), tol=1e-8, inner="f32")
+    x = to_host(x)
+    cbs, ref = cfg1_golden()
+    err = np.linalg.norm(x[cbs] - ref) / np.linalg.norm(ref)
+    res = _true_resid(dims, U, m, b, x)
+    announce(f"  iters={st.iters} ru={st.reliable_updates} resid={st.true_rel_resid:.3e} oracle-resid={res:.3e} "
+             f"sampled err={err:.3e}")
+    assert st.converged and st.true_rel_resid <= 1e-8 and res <= 1.01e-8
+    assert err <= 1e-6
+
+
+@pytest.mark.parametrize("lp,recon", [("f16", 12), ("bf16", 18), ("i16", 12)])
+def test_batched(lp, recon):
+    specs = [((8, 8, 8, 8), 521, [0.02, 0.05, 0.1]), ((6, 8, 4, 12), 522, [0.03]), ((4, 4, 4, 4), 523, [0.1])]
+    systems, host = [], []
+    for k, (dims, seed, masses) in enumerate(specs):
+        U = li.near_identity_links(dims, 0.3, seed)
+        G = gauge16(dims, U, lp, recon)
+        for j, m in enumerate(masses):
+            b = li.gaussian_even_source(dims, 530 + 10 * k + j)
+            systems.append((G, m, to_dev(b)))
+            host.append((dims, U, m, b))
+    announce(f"links16 batched {lp} r{recon}")
+    xs, stats = sp.cg_solve_batched(systems, tol=1e-8, inner="f32")
+    for (G, m, bd), (dims, U, _, b), x, st in zip(systems, host, xs, stats):
+        xr, _, _, _ = oracle.cg_solve(dims, U, m, b, tol=1e-12)
+        x1, _ = sp.cg_solve(G, m, bd, tol=1e-8, inner="f32")
+        err = rel_err_2(to_host(x), xr)
+        announce(f"  dims={dims} m={m}: iters={st.iters} err={err:.2e}")
+        assert st.converged and st.true_rel_resid <= 1e-8 and err <= 1e-6
+        assert rel_err_2(to_host(x), to_host(x1)) <= 1e-6
+
+
+@pytest.mark.parametrize("lp", ["f16", "bf16", "i16"])
+def test_schedules_and_source_scale(lp):
+    """Chunks of 1, 7 and 25 iterations (the recurrence of t restarted at every chunk end) reach the oracle's
+    answer; sources scaled by 1e-30 and 1e30 give solutions scaled the same way."""
+    dims = (8, 8, 8, 8)
+    U = li.near_identity_links(dims, 0.3, 541)
+    b = li.gaussian_even_source(dims, 542)
+    m = 0.02
+    G = gauge16(dims, U, lp, 12)
+    xr, _, _, _ = oracle.cg_solve(dims, U, m, b, tol=1e-12)
+    for chunk in (1, 7, 25):
+        x, st = sp.cg_solve(G, m, to_dev(b), tol=1e-8, inner="f32", poll_chunk=chunk)
+        err = rel_err_2(to_host(x), xr)
+        announce(f"links16 {lp} chunk {chunk}: iters={st.iters} err={err:.2e}")
+        assert st.converged and err <= 1e-6
+    for s in (1e-30, 1e30):
+        x, st = sp.cg_solve(G, m, to_dev(b * s), tol=1e-8, inner="f32")
+        err = rel_err_2(to_host(x) / s, xr)
+        announce(f"links16 {lp} scale {s:g}: iters={st.iters} err={err:.2e}")
+        assert st.converged and err <= 1e-6
+
+
+def test_packing_mismatch_rejected():
+    # 16-bit vectors need links of their own precision; FP64 iterations ignore the low packing
+    dims = (4, 4, 4, 4)
+    G = gauge16(dims, li.haar_links(dims, 551), "f16", 12)
+    b = to_dev(li.gaussian_even_source(dims, 552))
+    with pytest.raises(ValueError):
+        sp.cg_solve(G, 0.1, b, tol=1e-8, inner="bf16")
+    x, st = sp.cg_solve(G, 0.1, b, tol=1e-8, inner="f64")
+    assert st.converged
