@@ -37,11 +37,15 @@ def dslash_bytes_per_site(prec, recon):
     return 8 * LINK_BYTES[(prec, recon)] + 2 * VEC_BYTES[prec]
 
 
-def iteration_bytes_per_site(prec, recon):
-    """Algorithmic bytes per even site of one mixed-precision CG iteration: t = D_oe p (links, p, t);
-    x += alpha p, r -= alpha (m^2 p - D_eo t) (links, t, p, x and r read and written; x in FP32 for
-    every inner precision); p = r + beta p (r, p read, p written)."""
-    links, v, x = 8 * LINK_BYTES[(prec, recon)], VEC_BYTES[prec], VEC_BYTES["f32"]
+def iteration_bytes_per_site(prec, recon, link_prec=None):
+    """Algorithmic bytes per even site of one mixed-precision CG iteration. FP32 (and FP64) iterations take two
+    launches: t = D_oe r + beta t with p = r + beta p (links, r, t read and written, p read and written) and
+    x += alpha p, r -= alpha (m^2 p - D_eo t) (links, t, p, x and r read and written); x is FP32 for every
+    inner precision. 16-bit vector storage takes three: t = D_oe p, the same update, p = r + beta p.
+    link_prec: the links' storage precision when it differs from the vectors' (16-bit links, FP32 vectors)."""
+    links, v, x = 8 * LINK_BYTES[(link_prec or prec, recon)], VEC_BYTES[prec], VEC_BYTES["f32"]
+    if prec in ("f32", "f64"):
+        return (links + v + 2 * v + 2 * v) + (links + v + v + 2 * x + 2 * v)
     return (links + 2 * v) + (links + 2 * v + 2 * x + 2 * v) + 3 * v
 
 
@@ -90,50 +94,123 @@ def control_links(dims, eps, seed, dev, torch):
     return out
 
 
-def time_dslash(sp, torch, G, prec, inp, out, reps, stream, flush=None):
-    """Mean time of one half-Dslash launch over `reps` back-to-back launches (HIP events on the launch
-    stream), or, with a flush buffer, the median over launches each timed alone after reading the buffer
-    (1 GiB of float32, four times the Infinity Cache; read, not written, so that the cache holds no dirty
-    lines whose write-back the launch would pay) so that links and vectors come from HBM. The
-    single-launch figure includes the event pair's own overhead (G = None measures that alone)."""
-    for _ in range(10 if G is not None else 0):
+def time_dslash(sp, torch, G, prec, inp, out, reps, stream):
+    """Mean duration of one half-Dslash launch over `reps` back-to-back launches (HIP events on the launch
+    stream). Between launches the links stay in the Infinity Cache when they fit in it (the warm figure)."""
+    for _ in range(10):
         sp.dslash_packed(G, prec, inp, 1, out)
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    if flush is None:
-        e0.record(stream)
-        for _ in range(reps):
-            sp.dslash_packed(G, prec, inp, 1, out)
-        e1.record(stream)
-        e1.synchronize()
-        return e0.elapsed_time(e1) / 1e3 / reps
-    ts = []
-    for k in range(reps):
-        flush.sum()
-        e0.record(stream)
-        if G is not None:
-            sp.dslash_packed(G, prec, inp, 1, out)
-        e1.record(stream)
-        e1.synchronize()
-        ts.append(e0.elapsed_time(e1) / 1e3)
-    ts.sort()
-    return ts[len(ts) // 2]
-
-
-def copy_bandwidth(torch, dev, stream, n=1 << 30, reps=10):
-    """Device-to-device copy of n bytes: GB/s counting the read and the write."""
-    src = torch.ones(n, dtype=torch.uint8, device=dev)
-    dst = torch.empty_like(src)
-    for _ in range(3):
-        dst.copy_(src)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(stream)
     for _ in range(reps):
-        dst.copy_(src)
+        sp.dslash_packed(G, prec, inp, 1, out)
     e1.record(stream)
     e1.synchronize()
-    return 2 * n * reps / (e0.elapsed_time(e1) / 1e3) / 1e9
+    return e0.elapsed_time(e1) / 1e3 / reps
+
+
+def time_flushed(torch, fn, flush, stream, reps=60, trials=5):
+    """Net duration of one launch of fn when the Infinity Cache has been flushed just before it, so that every
+    byte comes from HBM: (reps pairs of flush + launch) minus (reps flushes alone), both timed with HIP events
+    on the launch stream, per launch; median over trials. The flush reads a 1 GiB buffer (four times the
+    Infinity Cache; read, not written, so the cache holds no dirty lines whose write-back the launch would pay).
+    Differencing removes the flush and the events' own cost; the launch's start after the flush stays in."""
+    for _ in range(3):
+        flush.sum()
+        fn()
+    res = []
+    for _ in range(trials):
+        f0, f1, e0, e1 = (torch.cuda.Event(enable_timing=True) for _ in range(4))
+        f0.record(stream)
+        for _ in range(reps):
+            flush.sum()
+        f1.record(stream)
+        e0.record(stream)
+        for _ in range(reps):
+            flush.sum()
+            fn()
+        e1.record(stream)
+        e1.synchronize()
+        res.append((e0.elapsed_time(e1) - f0.elapsed_time(f1)) / 1e3 / reps)
+    res.sort()
+    return res[len(res) // 2]
+
+
+PREC_CODE = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3}
+
+
+def tune_key(dims, lp, recon, vp):
+    return f"{dims[0]}x{dims[1]}x{dims[2]}x{dims[3]}/l{PREC_CODE[lp]}/r{recon}/v{PREC_CODE[vp]}"
+
+
+def pin_launch(sp, key, cfg):
+    """Make the library use launch configuration cfg ({"nt", "remap", "stream"}) for one tuning key, through a
+    temporary table file (sp_tune_load merges it into the process's table)."""
+    import tempfile
+
+    with tempfile.NamedTemporaryFile("w", suffix=".json", delete=False) as f:
+        f.write("{\n  \"%s\": {\"nt\": %d, \"remap\": %d, \"stream\": %d}\n}\n"
+                % (key, cfg["nt"], cfg["remap"], cfg.get("stream", 0)))
+        path = f.name
+    try:
+        sp.tune_load(path)
+    finally:
+        os.unlink(path)
+
+
+def tuned_entry(path, key):
+    """The tuned launch of key in a table file, or the library's default."""
+    try:
+        with open(path) as f:
+            return {"nt": 256, "remap": 1, "stream": 0, **json.load(f)[key]}
+    except (OSError, KeyError, ValueError):
+        return {"nt": 256, "remap": 1, "stream": 0}
+
+
+def stream_ceiling(sp, torch, dev, stream, flush, log, nbytes=2 << 30, small_bytes=None):
+    """The library's own streaming kernels (sp_stream_probe: read, copy, triad, 16-byte words per lane, 1, 2, 4
+    or 8 words per lane) over nbytes per buffer, back to back: the attainable HBM rates. With small_bytes, also
+    the read probe over a buffer of that size after an Infinity Cache flush (net, as time_flushed): what a
+    cold read of the half-Dslash's size attains."""
+    n = nbytes // 4
+    a = torch.ones(n, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    c = torch.ones_like(a)
+    out = {}
+    for kind, per in (("read", 16), ("copy", 32), ("triad", 48)):
+        best = None
+        for k in (1, 2, 4, 8):
+            fn = lambda: sp.stream_probe(kind, k, a, b, c if kind == "triad" else None)
+            for _ in range(2):
+                fn()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(10):
+                fn()
+            e1.record(stream)
+            e1.synchronize()
+            gbs = per * (nbytes // 16) / (e0.elapsed_time(e1) / 1e3 / 10) / 1e9
+            if best is None or gbs > best[0]:
+                best = (gbs, k)
+        out[kind] = {"GBs": best[0], "words_per_lane": best[1], "bytes_per_buffer": nbytes,
+                     "hbm_frac": best[0] / HBM_PEAK_GBS}
+    del a, b, c
+    if small_bytes:
+        n = small_bytes // 4
+        a = torch.ones(n, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        best = None
+        for k in (1, 2, 4, 8):
+            t = time_flushed(torch, lambda: sp.stream_probe("read", k, a, b), flush, stream, reps=30, trials=3)
+            gbs = small_bytes / t / 1e9
+            if best is None or gbs > best[0]:
+                best = (gbs, k, t)
+        out["read_cold_small"] = {"GBs": best[0], "words_per_lane": best[1], "us": best[2] * 1e6,
+                                  "bytes": small_bytes, "hbm_frac": best[0] / HBM_PEAK_GBS}
+        del a, b
+    log("stream probe: " + ", ".join(f"{k} {v['GBs']:.0f} GB/s" for k, v in out.items()))
+    return out
 
 
 KERNEL_SOURCES = ["paper_1511_00088_amd/csrc/sp_device.h", "paper_1511_00088_amd/csrc/sp_kernels.h",
@@ -299,6 +376,35 @@ def bench_gradient(sp, li, torch, dev, log):
     return {"dims": list(c["dims"]), "s": t, "note": "forward solve + adjoint solve to 1e-10 + force kernels"}
 
 
+
+def bench_large_lattices(sp, torch, dev, tune_file, log, ws):
+    """Mixed FP32 recon-12 solves (m = 0.01, Gaussian source, tol 1e-8) on the 32^3x64 control lattice and the
+    paper's 28^3x96 production lattice (Sec. 4), whose link fields exceed the Infinity Cache: time per iteration
+    against the workload's, and the iteration's fraction of HBM peak at its algorithmic bytes."""
+    out = {}
+    ib = iteration_bytes_per_site("f32", 12)
+    for dims, seed in (((32, 32, 32, 64), 71), ((28, 28, 28, 96), 72)):
+        lat = sp.Lattice(dims)
+        links = control_links(dims, 0.3, seed, dev, torch)
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(seed + 100)
+        bsrc = torch.randn(lat.Vh, 3, dtype=torch.complex128, device=dev, generator=gen)
+        G = sp.Gauge(lat, links, lo_prec="f32", recon=12)
+        del links
+        sp.cg_solve(G, 0.01, bsrc, tol=1e-8, inner="f32", workspace=ws)
+        torch.cuda.synchronize()
+        ts, (_, st) = timed_solves(torch, lambda: sp.cg_solve(G, 0.01, bsrc, tol=1e-8, inner="f32", workspace=ws), 2)
+        t = min(ts)
+        t_it = t / max(st.iters, 1)
+        out[f"{dims[0]}x{dims[1]}x{dims[2]}x{dims[3]}"] = {
+            "s": t, "iters": st.iters, "reliable_updates": st.reliable_updates, "converged": st.converged,
+            "true_rel_resid": st.true_rel_resid, "us_per_iteration": t_it * 1e6,
+            "iteration_hbm_frac": ib * lat.Vh / t_it / 1e9 / HBM_PEAK_GBS}
+        log(f"large lattice {dims}: {t * 1e3:.1f} ms, {st.iters} iterations, {t_it * 1e6:.1f} us/iteration "
+            f"({ib * lat.Vh / t_it / 1e9 / HBM_PEAK_GBS:.3f} of peak)")
+        del G, bsrc
+    return out
+
 def bench_packing(sp, torch, lat, links, b, inner, recon, stream, log):
     """Packing, done once per gauge field (links) or per source and solution (vectors) and not part of the
     time-to-solution: natural complex128 links to the FP64 recon-18 layout and to the inner precision's
@@ -463,25 +569,41 @@ def main():
     # --- dominant kernel: half-Dslash in the inner precision, HIP events on the launch stream ---
     inp = sp.pack_vec(lat, b, args.inner)
     out = torch.empty_like(inp)
-    t_d = time_dslash(sp, torch, G, args.inner, inp, out, args.dslash_reps, stream)
     bps = dslash_bytes_per_site(args.inner, args.recon)
-    achieved = bps * lat.Vh / t_d / 1e9
-    gflops = FLOP_PER_SITE * lat.Vh / t_d / 1e9
+    alg_bytes = bps * lat.Vh
+    flush = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+    # both link-load policies of the tuned launch: warm (back-to-back; the 20^3x64 links, 98 MB in FP32
+    # recon-12, stay in the Infinity Cache, the solver's situation) and cold (each launch after a 1 GiB read
+    # that flushes the Infinity Cache, net of the flush: every byte from HBM, the roofline figure)
+    key = tune_key(dims, args.inner, args.recon, args.inner)
+    tuned = tuned_entry(args.tune_file, key)
+    policies = {}
+    for pol, name in ((0, "cached"), (1, "streaming")):
+        pin_launch(sp, key, dict(tuned, stream=pol))
+        tw = time_dslash(sp, torch, G, args.inner, inp, out, args.dslash_reps, stream)
+        tf = time_flushed(torch, lambda: sp.dslash_packed(G, args.inner, inp, 1, out), flush, stream)
+        policies[name] = {"warm_us": tw * 1e6, "flushed_us": tf * 1e6, "warm_hbm_frac": alg_bytes / tw / 1e9 / HBM_PEAK_GBS,
+                          "flushed_hbm_frac": alg_bytes / tf / 1e9 / HBM_PEAK_GBS,
+                          "solver_uses": pol == tuned.get("stream", 0)}
+    pin_launch(sp, key, tuned)
+    solver_pol = "streaming" if tuned.get("stream", 0) else "cached"
+    best_pol = min(policies, key=lambda k: policies[k]["flushed_us"])
+    t_d = policies[solver_pol]["warm_us"] / 1e6
+    t_df = policies[best_pol]["flushed_us"] / 1e6
+    achieved = alg_bytes / t_df / 1e9
+    gflops = FLOP_PER_SITE * lat.Vh / t_df / 1e9
     # FP64 half-Dslash as well (the reliable-update and plain-FP64 kernel)
     inp64 = sp.pack_vec(lat, b, "f64")
     out64 = torch.empty_like(inp64)
     t_d64 = time_dslash(sp, torch, G64, "f64", inp64, out64, args.dslash_reps // 2, stream)
-    log(f"dslash {args.inner} r{args.recon}: {t_d * 1e6:.2f} us, {achieved:.0f} GB/s, {gflops:.0f} GFLOP/s; "
-        f"f64: {t_d64 * 1e6:.2f} us")
-    # the same launches with the Infinity Cache flushed before each, and a plain copy's bandwidth
-    flush = torch.ones(1 << 28, dtype=torch.float32, device=dev)
-    t_df = time_dslash(sp, torch, G, args.inner, inp, out, 30, stream, flush)
-    t_ev = time_dslash(sp, torch, None, args.inner, inp, out, 30, stream, flush)
-    copy_gbs = copy_bandwidth(torch, dev, stream)
-    log(f"dslash flushed: {t_df * 1e6:.2f} us ({bps * lat.Vh / t_df / 1e9:.0f} GB/s); copy {copy_gbs:.0f} GB/s")
-    dslash_extra = {"flushed_us": t_df * 1e6, "event_pair_us": t_ev * 1e6, "flushed_hbm_frac": bps * lat.Vh / t_df / 1e9 / HBM_PEAK_GBS,
-                    "copy_GBs": copy_gbs, "frac_of_copy": achieved / copy_gbs,
-                    "flushed_frac_of_copy": bps * lat.Vh / t_df / 1e9 / copy_gbs}
+    log(f"dslash {args.inner} r{args.recon}: flushed {t_df * 1e6:.2f} us ({achieved:.0f} GB/s), warm "
+        f"{t_d * 1e6:.2f} us ({alg_bytes / t_d / 1e9:.0f} GB/s); f64 warm {t_d64 * 1e6:.2f} us")
+    probe = stream_ceiling(sp, torch, dev, stream, flush, log, small_bytes=alg_bytes)
+    dslash_extra = {"flushed_us": t_df * 1e6, "flushed_hbm_frac": achieved / HBM_PEAK_GBS, "policies": policies,
+                    "tuned_launch": tuned,
+                    "warm_us": t_d * 1e6, "warm_GBs": alg_bytes / t_d / 1e9, "warm_hbm_frac": alg_bytes / t_d / 1e9 / HBM_PEAK_GBS,
+                    "warm_gflops": FLOP_PER_SITE * lat.Vh / t_d / 1e9}
+    control = None
     if not args.no_extras:
         # control lattice 32^3x64: links of every packing are more than the 256 MB Infinity Cache
         cd = (32, 32, 32, 64)
@@ -495,7 +617,7 @@ def main():
             co = torch.empty_like(ci)
             cb = dslash_bytes_per_site(args.inner, rc)
             tc = time_dslash(sp, torch, Gc, args.inner, ci, co, 100, stream)
-            tcf = time_dslash(sp, torch, Gc, args.inner, ci, co, 20, stream, flush)
+            tcf = time_flushed(torch, lambda: sp.dslash_packed(Gc, args.inner, ci, 1, co), flush, stream, reps=20)
             ctl[f"{args.inner}_r{rc}"] = {"us": tc * 1e6, "hbm_frac": cb * clat.Vh / tc / 1e9 / HBM_PEAK_GBS,
                                           "flushed_us": tcf * 1e6,
                                           "flushed_hbm_frac": cb * clat.Vh / tcf / 1e9 / HBM_PEAK_GBS}
@@ -503,6 +625,7 @@ def main():
             del Gc, ci, co
         del clinks
         dslash_extra["control_32x32x32x64"] = ctl
+        control = ctl.get(f"{args.inner}_r{args.recon}")
         # every packing at the workload shape, back-to-back (tuned launch of each)
         allc = {}
         for prec, rc in LINK_BYTES:
@@ -555,10 +678,32 @@ def main():
                 log(f"{prec} r{rc}: {tl * 1e3:.2f} ms/solve iters={stl.iters} err={el:.2e}")
                 del Gl
         extra["storage_16bit"] = low
+        # 16-bit links with FP32 vectors and arithmetic (the links are most of each iteration's bytes)
+        l16 = {}
+        for lp in ("f16", "bf16"):
+            for rc in (12, 18):
+                Gl = sp.Gauge(lat, G64_links(), lo_prec=lp, recon=rc)
+                sp.cg_solve(Gl, mass, b, tol=tol, inner="f32", workspace=ws)
+                torch.cuda.synchronize()
+                pl, (xl, stl) = timed_solves(
+                    torch, lambda: sp.cg_solve(Gl, mass, b, tol=tol, inner="f32", workspace=ws), max(1, args.steps))
+                tl, tl_se = mean_stderr(pl)
+                el = float(torch.linalg.norm(xl - xref) / torch.linalg.norm(xref))
+                ib = iteration_bytes_per_site("f32", rc, lp)
+                l16[f"links_{lp}_r{rc}"] = {"s": tl, "s_stderr": tl_se, "solves": len(pl), "iters": stl.iters,
+                                            "reliable_updates": stl.reliable_updates,
+                                            "true_rel_resid": stl.true_rel_resid, "err_vs_fp64_1e12": el,
+                                            "speedup_vs_inner": t_mixed / tl,
+                                            "iteration_bytes_per_site": ib,
+                                            "iteration_hbm_frac": ib * lat.Vh / (tl / max(stl.iters, 1)) / 1e9 / HBM_PEAK_GBS}
+                log(f"links {lp} r{rc} + f32 vectors: {tl * 1e3:.2f} ms/solve iters={stl.iters} err={el:.2e}")
+                del Gl
+        extra["links_16bit_vectors_f32"] = l16
         extra["hyp"] = bench_hyp(sp, torch, lat, G64_links(), stream, log)
         extra["npr"] = bench_npr(sp, torch, lat, G64_links(), stream, log)
         extra["batched"] = bench_batched(sp, li, torch, dev, log)
         extra["gradient"] = bench_gradient(sp, li, torch, dev, log)
+        extra["large_lattices"] = bench_large_lattices(sp, torch, dev, args.tune_file, log, ws)
         extra["packing"] = bench_packing(sp, torch, lat, G64_links(), b, args.inner, args.recon, stream, log)
 
     cpu = None
@@ -566,23 +711,31 @@ def main():
         import oracle
 
         oracle.build(force=False)
-        n_it = 40
-        log(f"CPU oracle: half-Dslash and {n_it} FP64 CG iterations on {dims}")
         bh = c["source"]
+        # the whole FP64 solve of the same system to the same 1e-8 true residual, single-threaded
+        log(f"CPU oracle: FP64 CG on {dims} to {tol} (one core)")
+        t0 = time.perf_counter()
+        _, status, it_cpu, res_cpu = oracle.cg_solve(dims, c["links"], mass, bh, tol=tol)
+        t_cpu = time.perf_counter() - t0
+        # cross-check: 40 iterations, scaled per iteration
+        n_it = 40
+        t0 = time.perf_counter()
+        oracle.cg_solve(dims, c["links"], mass, bh, tol=1e-30, max_iter=n_it)
+        t_cpu40 = time.perf_counter() - t0
         t0 = time.perf_counter()
         oracle.dslash_eo(dims, c["links"], bh, 1)
         t_cpu_d = time.perf_counter() - t0
-        t0 = time.perf_counter()
-        _, status, it, _ = oracle.cg_solve(dims, c["links"], mass, bh, tol=1e-30, max_iter=n_it)
-        t_cpu = time.perf_counter() - t0
-        iters_needed = extra.get("fp64_iters", st.iters)
-        per_iter = t_cpu / (n_it + 2)  # n_it iterations + initial and final residual applications
-        cpu = {"value": per_iter * iters_needed, "unit": "s", "cores": 1, "kind": "oracle",
-               "sample": f"{n_it} FP64 CG iterations of the single-threaded oracle on {dims[0]}^3x{dims[3]} "
-                         f"({t_cpu:.1f} s), scaled to the {iters_needed} iterations FP64 CG needs for 1e-8; "
-                         f"host {cpu_model()}, {os.cpu_count()} logical CPUs",
-               "dslash_s": t_cpu_d, "dslash_gflops": FLOP_PER_SITE * lat.Vh / t_cpu_d / 1e9}
-        log(f"CPU oracle: {per_iter * 1e3:.1f} ms/iteration -> {cpu['value']:.1f} s")
+        cpu = {"value": t_cpu, "unit": "s", "cores": 1, "kind": "oracle",
+               "sample": f"the whole single-threaded FP64 oracle CG solve of the same {dims[0]}^3x{dims[3]} system from "
+                         f"x = 0 to a true relative residual of {tol} ({it_cpu} iterations, residual {res_cpu:.3e}, "
+                         f"status {status}); host {cpu_model()}, {os.cpu_count()} logical CPUs, one used",
+               "iters": it_cpu, "true_rel_resid": res_cpu, "status": status, "host": cpu_model(),
+               "host_logical_cpus": os.cpu_count(),
+               "per_iteration_s": t_cpu / max(it_cpu + 2, 1),
+               "per_iteration_s_40_iteration_sample": t_cpu40 / (n_it + 2),
+               "dslash_s": t_cpu_d, "dslash_gflops": FLOP_PER_SITE * lat.Vh / t_cpu_d / 1e9,
+               "gpu_speedup_mixed": t_cpu / t_mixed}
+        log(f"CPU oracle: {t_cpu:.1f} s, {it_cpu} iterations, residual {res_cpu:.2e}")
 
     ibps = iteration_bytes_per_site(args.inner, args.recon)
     t_it = t_mixed / max(st.iters, 1)
@@ -610,14 +763,27 @@ def main():
         "true_rel_resid": st.true_rel_resid,
         "solve_s_min": min(per) if per else None,
         "cg_gflops": CG_FLOP_PER_SITE * lat.V * st.iters / t_mixed / 1e9,
-        "dslash": {"prec": args.inner, "recon": args.recon, "us": t_d * 1e6, "gflops": gflops,
+        "dslash": {"prec": args.inner, "recon": args.recon, "us": t_df * 1e6, "gflops": gflops,
                    "bytes_per_site": bps, "hbm_frac": achieved / HBM_PEAK_GBS, "f64_us": t_d64 * 1e6,
                    "f64_gflops": FLOP_PER_SITE * lat.Vh / t_d64 / 1e9, **dslash_extra},
         "iteration": {"bytes_per_site": ibps, "us": t_it * 1e6, "achieved_GBs": ibps * lat.Vh / t_it / 1e9,
                       "hbm_frac": ibps * lat.Vh / t_it / 1e9 / HBM_PEAK_GBS,
                       "note": "whole solve time / iterations (reliable updates, set-up and polling included)"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": f"half-Dslash {args.inner} recon-{args.recon}, {dims[0]}^3x{dims[3]}, {lat.Vh} output sites, "
+                               f"{bps} algorithmic B/site",
+                     "measured": "each launch after an Infinity Cache flush, net of the flush (HIP events, differencing)",
+                     "link_loads": best_pol,
+                     "solver_link_loads": solver_pol,
+                     "solver_config_flushed_frac": policies[solver_pol]["flushed_hbm_frac"],
+                     "warm_frac": alg_bytes / t_d / 1e9 / HBM_PEAK_GBS,
+                     "control_32x32x32x64_flushed_frac": control["flushed_hbm_frac"] if control else None,
+                     "attainable_read_GBs": probe["read"]["GBs"],
+                     "attainable_cold_read_same_bytes_GBs": probe["read_cold_small"]["GBs"],
+                     "frac_of_attainable_read": achieved / probe["read"]["GBs"],
+                     "frac_of_attainable_cold_read_same_bytes": achieved / probe["read_cold_small"]["GBs"]},
+        "stream_probe": probe,
         "cpu_baseline": cpu,
     }
     line.update(extra)
