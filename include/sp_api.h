@@ -32,6 +32,10 @@
  *  - Host threads: the solves (sp_cg_solve, sp_cg_solve_batched and the even solve inside sp_full_solve)
  *    hold one library-wide lock from entry to return, so solves issued from several host threads run
  *    one after another; sp_dslash takes the lock only to read the tuning table.
+ *  - Diagnostics (environment, read once): SP_LOG=1 prints one line per solved system to stderr (status,
+ *    iterations, reliable updates, true residual, time), SP_LOG=2 also one line per chunk poll. Each solve and
+ *    each chunk is a roctx range (rocprofv3 --marker-trace) when the roctx library can be loaded; SP_ROCTX=0
+ *    turns the ranges off.
  */
 #ifndef SP_API_H
 #define SP_API_H
@@ -88,8 +92,8 @@ typedef struct {
  *             number ~1.6e5) but stalls near m = 1e-3 (~1.6e7), where SP_F32 and SP_F64 still converge
  *  delta      reliable update when |r_iterated| < delta * |r at the last update| (0 disables; ignored
  *             for SP_F64; checked at the end of each poll chunk)
- *  ru_every   reliable update at least every ru_every iterations (ignored for SP_F64; <= 0 picks 100;
- *             checked at the end of each poll chunk)
+ *  ru_every   reliable update at least every ru_every iterations (ignored for SP_F64; <= 0 picks 100, or
+ *             50 for FP32 iterations on SP_I16 links; checked at the end of each poll chunk)
  *  poll_chunk iterations per device-side chunk (one hipGraph launch) between host convergence polls
  *             (<= 0 picks 25)
  *  use_x0     1: x_e holds the initial guess on entry; 0: start from zero
@@ -97,9 +101,9 @@ typedef struct {
  * A reliable update also runs whenever the iterated residual reaches tol, at the iteration cap, and (for
  * SP_F32, SP_F16, SP_BF16) when the iterated residual falls three decades below the true residual of the
  * last update. After
- * it, FP32 iterations on FP32 links keep the search direction (re-orthogonalised against the new residual);
- * 16-bit storage of the vectors or of the links restarts it from the residual (a kept direction stalls when
- * the rounded links move the operator by more than its smallest eigenvalue). */
+ * it, FP32 iterations on FP32 or SP_I16 links keep the search direction (re-orthogonalised against the new
+ * residual); FP16 or BF16 storage of the vectors or of the links restarts it from the residual (a kept
+ * direction stalls when the rounded links move the operator by much more than its smallest eigenvalue). */
 typedef struct {
     double tol;
     int32_t max_iter;
@@ -262,6 +266,13 @@ int sp_npr_path_links(const sp_geom* g, const double* links_nat, void* uad, void
  * layout, no conjugation implied). out: device, complex128 [n][V/16]. Asynchronous on stream. */
 int sp_npr_contract(const sp_geom* g, const void* uad, int n, const double* chib1, const double* chi2,
                     const double* chib3, const double* chi4, const int32_t* labels, double* out, void* stream);
+
+/* The same contraction with the path links built inside it, per hypercube in on-chip memory, from the natural
+ * links (device complex128 [4][V][3][3]): no path-link array is written or read (36 KB per hypercube, 1.18 GB at
+ * 20^3x64). The paths are rebuilt by every call, so when many calls share one gauge field (other labels or other
+ * field sets) sp_npr_path_links once and sp_npr_contract per call move fewer bytes in total. Asynchronous. */
+int sp_npr_contract_links(const sp_geom* g, const double* links_nat, int n, const double* chib1, const double* chi2,
+                          const double* chib3, const double* chi4, const int32_t* labels, double* out, void* stream);
 
 /* Workspace bytes for sp_full_solve. */
 size_t sp_full_workspace_bytes(const sp_geom* g, const sp_gauge* U, const sp_cg_params* params);

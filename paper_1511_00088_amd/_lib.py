@@ -89,6 +89,7 @@ SIGNATURES = {
     "sp_npr_path_bytes": (SZ, [PG]),
     "sp_npr_path_links": (I, [PG, P, P, P]),
     "sp_npr_contract": (I, [PG, P, I, P, P, P, P, ctypes.POINTER(ctypes.c_int32), P, P]),
+    "sp_npr_contract_links": (I, [PG, P, I, P, P, P, P, ctypes.POINTER(ctypes.c_int32), P, P]),
     "sp_tune_dslash": (I, [PG, PU, I, P, P, P, ctypes.POINTER(D)]),
     "sp_tune_save": (I, [ctypes.c_char_p]),
     "sp_tune_load": (I, [ctypes.c_char_p]),

@@ -325,6 +325,20 @@ def npr_path_links(lat: Lattice, links: torch.Tensor) -> torch.Tensor:
     return out
 
 
+def npr_contract_links(lat: Lattice, links: torch.Tensor, chib1, chi2, chib3, chi4, labels) -> torch.Tensor:
+    """O_i(z) as npr_contract, with the path links built inside the contraction from the links [4][V][3][3]
+    (sp_npr_contract_links): nothing but the result is written."""
+    _check_c128(links, (4, lat.V, 3, 3), "links")
+    n = chib1.shape[0]
+    for name, f in (("chib1", chib1), ("chi2", chi2), ("chib3", chib3), ("chi4", chi4)):
+        _check_c128(f, (n, lat.V, 3), name)
+    out = torch.empty(n, lat.V // 16, dtype=torch.complex128, device=links.device)
+    lab = (ctypes.c_int32 * 4)(*[int(x) for x in labels])
+    L.check(L.load().sp_npr_contract_links(ctypes.byref(lat.geom), _ptr(links), int(n), _ptr(chib1), _ptr(chi2),
+                                           _ptr(chib3), _ptr(chi4), lab, _ptr(out), _stream()), "sp_npr_contract_links")
+    return out
+
+
 def npr_contract(lat: Lattice, uad: torch.Tensor, chib1, chi2, chib3, chi4, labels) -> torch.Tensor:
     """O_i(z) of the one-colour-trace four-fermion contraction (sp_npr_contract): fields complex128 [n][V][3],
     labels (S1, F1, S2, F2) -> complex128 [n][V/16]."""

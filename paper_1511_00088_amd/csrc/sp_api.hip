@@ -37,6 +37,8 @@
 #include <string>
 #include <vector>
 
+#include <dlfcn.h>
+
 #include "sp_entry.h"
 
 using namespace sp;
@@ -44,6 +46,59 @@ using namespace sp;
 namespace {
 
 thread_local std::string g_last_error;
+
+// ---------------------------------------------------------------------------------------------------
+// Diagnostics: a host log on stderr (SP_LOG=1: one line per solve; SP_LOG=2: also one per chunk poll) and roctx
+// ranges per solve and per chunk for rocprofv3 --marker-trace, from the roctx library when it can be loaded (no
+// link-time dependency; SP_ROCTX=0 turns the ranges off).
+// ---------------------------------------------------------------------------------------------------
+int log_level() {
+    static const int level = [] {
+        const char* e = getenv("SP_LOG");
+        return e ? atoi(e) : 0;
+    }();
+    return level;
+}
+
+void log_line(int level, const char* fmt, ...) {
+    if (log_level() < level) return;
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    fprintf(stderr, "[libstagcg] %s\n", buf);
+}
+
+struct Roctx {
+    int (*push)(const char*) = nullptr;
+    int (*pop)() = nullptr;
+    Roctx() {
+        const char* e = getenv("SP_ROCTX");
+        if (e && atoi(e) == 0) return;
+        void* h = dlopen("librocprofiler-sdk-roctx.so.1", RTLD_NOW | RTLD_LOCAL | RTLD_NOLOAD);
+        if (!h) h = dlopen("librocprofiler-sdk-roctx.so.1", RTLD_NOW | RTLD_LOCAL);
+        if (!h) return;
+        push = (int (*)(const char*))dlsym(h, "roctxRangePushA");
+        pop = (int (*)())dlsym(h, "roctxRangePop");
+        if (!push || !pop) push = nullptr, pop = nullptr;
+    }
+};
+const Roctx& roctx() {
+    static const Roctx r;
+    return r;
+}
+
+// A roctx range for the lifetime of the object.
+struct TraceRange {
+    bool on;
+    explicit TraceRange(const char* msg) : on(roctx().push != nullptr) {
+        if (on) roctx().push(msg);
+    }
+    ~TraceRange() {
+        if (on) roctx().pop();
+    }
+};
 
 int fail(int code, const char* fmt, ...) {
     char buf[512];
@@ -246,12 +301,11 @@ int make_layout(int nsys, const sp_system* systems, const sp_cg_params* prm, int
         const int lp = prm->inner == SP_F64 ? SP_F64 : G.U->lo_prec;
         const int rc = prm->inner == SP_F64 ? 18 : G.U->recon;
         L->cfg = n_rhs_max > 1 ? tuned_cfg_batched(G.g, lp, rc, prm->inner) : tuned_cfg(G.g, lp, rc, prm->inner);
-        // one system: 256-thread blocks when they admit the fused iteration and the tuned shape does not
-        // (the block size moves the operator by a few percent at most, the fused iteration saves a
-        // finalize launch per iteration)
-        if (n_rhs_max == 1 && blocks_for(G.g.Vh, L->cfg.nt) > FUSED_PARTIALS * L->cfg.nt &&
-            blocks_for(G.g.Vh, 256) <= FUSED_PARTIALS * 256)
-            L->cfg.nt = 256;
+        // one system: 256-thread blocks whenever they admit the fused iteration, whose launches have every block
+        // sum the partials of all blocks (smaller blocks mean more partials per block); the block order and the
+        // link-load policy stay the tuned ones. Measured: FP16 links with 128-thread blocks (the plain operator's
+        // tuned shape) took the 20^3x64 solve from 21.9 to 25.8 ms.
+        if (n_rhs_max == 1 && blocks_for(G.g.Vh, 256) <= FUSED_PARTIALS * 256) L->cfg.nt = 256;
     }
     int blk = 0;
     for (auto& G : L->groups) {
@@ -496,15 +550,18 @@ SolverState initial_state(const sp_system& s, const sp_cg_params* prm) {
     st.floor2 = prm->inner != SP_F64 ? 1e-6 : 0.0;  // |r| three decades below the last true residual
     st.m2 = s.mass * s.mass;
     st.max_iter = prm->max_iter;
+    // FP32 iterations on 16-bit fixed-point links keep the direction and update every 50 iterations (their
+    // links are within 2^-16 of the true ones); FP16 and BF16 storage, of the vectors or of the links, moves
+    // the inner operator by about 2^-11 |A| or more, far more than the smallest eigenvalue m^2 of a light-quark
+    // system, and a direction kept across an update then stalls the solve: they restart it (p = r) at every
+    // reliable update
+    const bool fixed16_links = prm->inner == SP_F32 && s.U && s.U->lo_prec == SP_I16;
+    const bool float16_links = prm->inner == SP_F32 && s.U && (s.U->lo_prec == SP_F16 || s.U->lo_prec == SP_BF16);
     int every = prm->ru_every;
     if (prm->inner == SP_F64) every = INT_MAX;
-    else if (every <= 0) every = 100;
+    else if (every <= 0) every = fixed16_links ? 50 : 100;
     st.ru_every = every;
-    // 16-bit storage of the vectors or of the links restarts the direction at every reliable update: the
-    // rounded links move the inner operator by about 2^-11 |A| (FP16), far more than the smallest eigenvalue
-    // m^2 of a light-quark system, and a direction kept across an update then stalls the solve
-    const bool links16 = prm->inner == SP_F32 && s.U && is_16bit_link(s.U->lo_prec);
-    st.restart = (prm->inner == SP_F16 || prm->inner == SP_BF16 || links16) ? 1 : 0;
+    st.restart = (prm->inner == SP_F16 || prm->inner == SP_BF16 || float16_links) ? 1 : 0;
     return st;
 }
 
@@ -532,6 +589,11 @@ int solve_impl(int nsys, const sp_system* systems, const sp_cg_params* prm, sp_c
     Layout L;
     int rc = make_layout(nsys, systems, prm, batched ? NB : 1, &L);
     if (rc) return rc;
+    char range[160];
+    snprintf(range, sizeof range, "%s %dx%dx%dx%d inner=%d links=%d/r%d systems=%d", batched ? "sp_cg_solve_batched" : "sp_cg_solve",
+             L.groups[0].g.X, L.groups[0].g.Y, L.groups[0].g.Z, L.groups[0].g.T, prm->inner,
+             prm->inner == SP_F64 ? SP_F64 : L.groups[0].U->lo_prec, prm->inner == SP_F64 ? 18 : L.groups[0].U->recon, nsys);
+    const TraceRange solve_range(range);
     if (!ws) return fail(SP_ERR_WORKSPACE, "workspace is null");
     if (ws_bytes < L.total) return fail(SP_ERR_WORKSPACE, "workspace %zu bytes < required %zu", ws_bytes, L.total);
     if (((uintptr_t)ws) & 255) return fail(SP_ERR_INVALID_ARG, "workspace not 256-byte aligned");
@@ -647,8 +709,13 @@ int solve_impl(int nsys, const sp_system* systems, const sp_cg_params* prm, sp_c
                 break;
             }
         }
-        if (exec) HIP_TRY(hipGraphLaunch(exec, stream));
-        else HIP_TRY(batched ? enqueue_chunk(db, pl, chunk, stream) : enqueue_chunk(ds, pl, chunk, stream));
+        {
+            char cr[48];
+            snprintf(cr, sizeof cr, "chunk %ld", c);
+            const TraceRange chunk_range(cr);
+            if (exec) HIP_TRY(hipGraphLaunch(exec, stream));
+            else HIP_TRY(batched ? enqueue_chunk(db, pl, chunk, stream) : enqueue_chunk(ds, pl, chunk, stream));
+        }
         HIP_TRY(hipMemcpyAsync(slots[c & 1], base + L.states_off, sizeof(SolverState) * nsys, hipMemcpyDeviceToHost,
                                stream));
         HIP_TRY(hipEventRecord(ev.e[c & 1], stream));
@@ -660,6 +727,8 @@ int solve_impl(int nsys, const sp_system* systems, const sp_cg_params* prm, sp_c
         if (careful || c == 0) continue;
         HIP_TRY(hipEventSynchronize(ev.e[(c - 1) & 1]));
         SolverState* prev = slots[(c - 1) & 1];
+        log_line(2, "poll after chunk %ld: system 0 iter %d |r|^2 %.3e flags %d", c - 1, prev[0].iter, prev[0].rho_new,
+                 prev[0].flags);
         if (all_done(prev)) {
             poll = prev;
             break;
@@ -708,6 +777,12 @@ int solve_impl(int nsys, const sp_system* systems, const sp_cg_params* prm, sp_c
             o.true_rel_resid = st.bnorm2 > 0 ? std::sqrt(st.true_rho / st.bnorm2) : 0.0;
             o.seconds = secs;
         }
+    }
+    for (int i = 0; i < nsys && log_level() >= 1; ++i) {
+        const SolverState& st = poll[i];
+        log_line(1, "%s: system %d of %d: status %d, %d iterations, %d reliable updates, true residual %.3e, %.3f ms",
+                 range, i, nsys, status_of(st), st.iter, st.ru_count,
+                 st.bnorm2 > 0 ? std::sqrt(st.true_rho / st.bnorm2) : 0.0, secs * 1e3);
     }
     if (worst < 0) return fail(worst, "CG breakdown (Re<p,Ap> <= 0 or non-finite scalar)");
     return worst;
@@ -1209,12 +1284,14 @@ int sp_npr_path_links(const sp_geom* g, const double* links_nat, void* uad, void
     return SP_OK;
 }
 
-int sp_npr_contract(const sp_geom* g, const void* uad, int n, const double* chib1, const double* chi2,
-                    const double* chib3, const double* chi4, const int32_t* labels, double* out, void* stream) {
+static int npr_contract_any(const sp_geom* g, const void* uad, const double* links_nat, int n, const double* chib1,
+                            const double* chi2, const double* chib3, const double* chi4, const int32_t* labels,
+                            double* out, void* stream) {
     Geom G;
     int rc = check_geom(g, &G);
     if (rc) return rc;
-    if (!uad || !chib1 || !chi2 || !chib3 || !chi4 || !labels || !out) return fail(SP_ERR_INVALID_ARG, "null pointer");
+    if (!(uad || links_nat) || !chib1 || !chi2 || !chib3 || !chi4 || !labels || !out)
+        return fail(SP_ERR_INVALID_ARG, "null pointer");
     if (n < 1) return fail(SP_ERR_INVALID_ARG, "n must be >= 1");
     int lab[4];
     for (int k = 0; k < 4; ++k) {
@@ -1224,8 +1301,21 @@ int sp_npr_contract(const sp_geom* g, const void* uad, int n, const double* chib
     const double* f[4] = {chib1, chi2, chib3, chi4};
     for (int k = 0; k < 4; ++k)
         if (((uintptr_t)f[k]) & 15) return fail(SP_ERR_INVALID_ARG, "field %d not 16-byte aligned", k);
-    HIP_TRY(launch_npr_contract(G, uad, n, f, lab, out, (hipStream_t)stream));
+    if (((uintptr_t)uad) & 15 || ((uintptr_t)links_nat) & 15) return fail(SP_ERR_INVALID_ARG, "pointers not 16-byte aligned");
+    HIP_TRY(launch_npr_contract_from(G, uad, links_nat, n, f, lab, out, (hipStream_t)stream));
     return SP_OK;
+}
+
+int sp_npr_contract(const sp_geom* g, const void* uad, int n, const double* chib1, const double* chi2,
+                    const double* chib3, const double* chi4, const int32_t* labels, double* out, void* stream) {
+    if (!uad) return fail(SP_ERR_INVALID_ARG, "null pointer");
+    return npr_contract_any(g, uad, nullptr, n, chib1, chi2, chib3, chi4, labels, out, stream);
+}
+
+int sp_npr_contract_links(const sp_geom* g, const double* links_nat, int n, const double* chib1, const double* chi2,
+                          const double* chib3, const double* chi4, const int32_t* labels, double* out, void* stream) {
+    if (!links_nat) return fail(SP_ERR_INVALID_ARG, "null pointer");
+    return npr_contract_any(g, nullptr, links_nat, n, chib1, chi2, chib3, chi4, labels, out, stream);
 }
 
 }  // extern "C"

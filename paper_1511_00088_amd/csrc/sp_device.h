@@ -520,6 +520,14 @@ __host__ __device__ __forceinline__ float eta_sign(const Site& s, int mu) {
     return (e & 1) ? -1.0f : 1.0f;
 }
 
+// Directions whose gathers a single-system half operator keeps in flight together (the unroll of its direction
+// loop), by measurement: two where all four put too many values in registers (FP64: 384 values; FP32 recon-12 and
+// 16-bit links with FP32 vectors: the row rebuild and the unpacking lower the waves per SIMD) unless the links
+// stream past the caches, four otherwise.
+constexpr int unroll_dirs(int lp, int recon, int vp, bool nt) {
+    return (vp == F64 || (!nt && ((lp == F32 && recon == 12) || (vp == F32 && lp != F32)))) ? 2 : 4;
+}
+
 // ------------------------------------------------------------------------------------------------------
 // The half operator at one site:
 //   out(n) = 1/2 sum_mu eta_mu(n) [ s_f U_mu(n) in(n+mu) - s_b U_mu(n-mu)^dag in(n-mu) ]
@@ -533,7 +541,7 @@ __device__ __forceinline__ Vec3<typename Real<VP>::T> dslash_site(const Geom g, 
     using LF = LinkFmt<LP, RECON>;
     using VF = VecFmt<VP>;
     Vec3<R> acc = vzero<R>();
-    constexpr int UNROLL = (VP == F64 || (LP == F32 && RECON == 12 && !NT)) ? 2 : 4;
+    constexpr int UNROLL = unroll_dirs(LP, RECON, VP, NT);
 #pragma unroll UNROLL
     for (int mu = 0; mu < 4; ++mu) {
         R e = (R)eta_sign(s, mu);

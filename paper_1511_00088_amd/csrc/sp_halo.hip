@@ -117,7 +117,7 @@ __global__ __launch_bounds__(256) void k_dslash_halo(Shard sh, const void* links
     const Site s = site_of(g, p, cb);
     const int tg = sh.t0 + s.t;
     Vec3<R> acc = vzero<R>();
-    constexpr int UNROLL = (VP == F64 || (LP == F32 && RECON == 12 && !NT)) ? 2 : 4;
+    constexpr int UNROLL = unroll_dirs(LP, RECON, VP, NT);
 #pragma unroll UNROLL
     for (int mu = 0; mu < 4; ++mu) {
         const R e = (R)eta_sign(s, mu);

@@ -202,7 +202,7 @@ __global__ __launch_bounds__(256) void k_dslash(D d, int p, int in_slot, int out
 // one direction at a time for several systems (their gathers would not fit in registers otherwise); two at
 // a time in FP64, where all four put 384 values in flight and leave one wave per SIMD, and for FP32
 // recon-12, whose row rebuild makes four at a time cost 125-136 VGPRs (measured 3-4% slower)
-        constexpr int UNROLL = N == 1 ? ((VP == F64 || (LP == F32 && RECON == 12 && !NT)) ? 2 : 4) : 1;
+        constexpr int UNROLL = N == 1 ? unroll_dirs(LP, RECON, VP, NT) : 1;
 #pragma unroll UNROLL
         for (int mu = 0; mu < 4; ++mu) {
             R e = (R)eta_sign(s, mu);

@@ -78,5 +78,9 @@ size_t npr_path_bytes(const Geom& g);
 hipError_t launch_npr_paths(const Geom& g, const double* links, void* uad, hipStream_t s);
 hipError_t launch_npr_contract(const Geom& g, const void* uad, int n, const double* const f[4], const int labels[4],
                                double* out, hipStream_t s);
+// The same contraction from stored path links (uad, links null) or fused with their construction from the natural
+// links (links non-null, uad ignored).
+hipError_t launch_npr_contract_from(const Geom& g, const void* uad, const double* links, int n, const double* const f[4],
+                                    const int labels[4], double* out, hipStream_t s);
 
 }  // namespace sp

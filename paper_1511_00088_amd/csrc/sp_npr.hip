@@ -5,7 +5,7 @@
 // with M_{AB} = (1/4) tr(gamma_A^dag gamma_S gamma_B gamma_F^dag) and U_AD(z) the average over the shortest
 // paths from z_A to z_D of the ordered link products.
 //
-// Two launches:
+// Two launches, or one fused:
 //  * k_npr_paths: one block per hypercube, one thread per corner pair; the path average is built by the
 //    first-step recursion in LDS (U_mu(x) for a step +mu, U_mu(x - mu)^dag for a step -mu). Output
 //    [nz][256][9] double2: a hypercube's 256 matrices are one contiguous 36 KB block, written and read
@@ -14,6 +14,8 @@
 //    B = A xor S xor F, where it is a sign, so each thread owns one term: it keeps U_{A,D} and U_{C,B}
 //    (D = C xor S2 xor F2) in registers for every field set; the hypercube's 192 field values of up to
 //    NPR_CHUNK field sets are staged in LDS together, and one block reduction gives their O_i(z).
+//  * k_npr_fused: both in one block per hypercube; the path links stay in LDS (for a few field sets per call this
+//    saves the 36 KB per hypercube written by k_npr_paths and read back by k_npr_contract).
 // The signs come from the anticommutation relations: gamma_X gamma_Y = (-1)^s(X,Y) gamma_{X xor Y} with
 // s(X,Y) = #{mu > nu : X_mu = Y_nu = 1}, gamma_X^dag = (-1)^{n(n-1)/2} gamma_X for n = |X|, tr gamma_0 = 4.
 #include "sp_launch.h"
@@ -57,14 +59,15 @@ __device__ __forceinline__ void mat_ld(const double2* p, C (&m)[3][3], bool dag)
     }
 }
 
-// One block per hypercube, one thread per corner pair (A, D). The average over the k! shortest paths is
-// built from the first step: U_AD = (1/k) sum over the k directions mu in which A and D differ of
-// L(A -> A^mu) U_{A^mu, D}, where L is U_mu(z_A) when A_mu = 0 and U_mu(z_A - mu)^dag otherwise. Pairs are
-// filled in LDS in order of k, so every U_{A^mu, D} a thread needs is complete one barrier earlier.
-__global__ __launch_bounds__(256) void k_npr_paths(NprGeom g, const double2* __restrict__ U, double2* __restrict__ out) {
-    __shared__ double2 lk[32][9];    // the hypercube's 32 links: [mu][corner with bit mu = 0, squeezed]
-    __shared__ double2 P[256][9];    // U_AD, pair A * 16 + D
-    const int z = blockIdx.x, t = threadIdx.x, A = t >> 4, D = t & 15;
+// The path links of hypercube z into P (LDS, pair A * 16 + D), by the 256 threads of a block, one per corner pair
+// (A, D). The average over the k! shortest paths is built from the first step: U_AD = (1/k) sum over the k
+// directions mu in which A and D differ of L(A -> A^mu) U_{A^mu, D}, where L is U_mu(z_A) when A_mu = 0 and
+// U_mu(z_A - mu)^dag otherwise. Pairs are filled in order of k, so every U_{A^mu, D} a thread needs is complete one
+// barrier earlier. lk (LDS) receives the hypercube's 32 links: [mu][corner with bit mu = 0, squeezed]. Ends with a
+// barrier.
+__device__ __forceinline__ void build_paths(const NprGeom& g, const double2* __restrict__ U, int z, double2 (*lk)[9],
+                                            double2 (*P)[9]) {
+    const int t = threadIdx.x, A = t >> 4, D = t & 15;
     int zc[4];
     coarse_coords(g, z, zc);
     for (int e = t; e < 32 * 9; e += 256) {
@@ -112,9 +115,16 @@ __global__ __launch_bounds__(256) void k_npr_paths(NprGeom g, const double2* __r
         }
         __syncthreads();
     }
-    double2* o = out + (long)z * 256 * 9;
+}
+
+// One block per hypercube: the path links, written as one contiguous 36 KB block per hypercube.
+__global__ __launch_bounds__(256) void k_npr_paths(NprGeom g, const double2* __restrict__ U, double2* __restrict__ out) {
+    __shared__ double2 lk[32][9];
+    __shared__ double2 P[256][9];
+    build_paths(g, U, blockIdx.x, lk, P);
+    double2* o = out + (long)blockIdx.x * 256 * 9;
     const double2* src = &P[0][0];
-    for (int e = t; e < 256 * 9; e += 256) o[e] = src[e];
+    for (int e = threadIdx.x; e < 256 * 9; e += 256) o[e] = src[e];
 }
 
 struct NprArgs {
@@ -131,25 +141,16 @@ struct NprArgs {
 // latency, and one block reduction covers all of them.
 constexpr int NPR_CHUNK = 4;
 
-__global__ __launch_bounds__(256) void k_npr_contract(NprArgs a) {
-    const int z = blockIdx.x;
+// The contraction of hypercube z for every field set, by thread (A, C) of a block holding U_{A,D} and U_{C,B} in
+// registers; fs (LDS) stages the hypercube's field values of NPR_CHUNK field sets at a time.
+__device__ __forceinline__ void contract_sets(const NprArgs& a, int z, const C (&uad)[3][3], const C (&ucb)[3][3],
+                                              double2 (*fs)[4][16][3]) {
     const int A = threadIdx.x >> 4, Cc = threadIdx.x & 15;
     const int B = A ^ a.d1, D = Cc ^ a.d2;
-    __shared__ double2 fs[NPR_CHUNK][4][16][3];  // the hypercube's field values of a pass
     int zc[4];
     coarse_coords(a.g, z, zc);
     const int c0[4] = {2 * zc[0], 2 * zc[1], 2 * zc[2], 2 * zc[3]};
     const int base = lex4(a.g, c0);  // z_0
-    // U_{A,D} and U_{C,B}, kept in registers for every field set
-    C uad[3][3], ucb[3][3];
-    const double2* blk = a.uad + (long)z * 256 * 9;
-#pragma unroll
-    for (int j = 0; j < 9; ++j) {
-        const double2 v = blk[(A * 16 + D) * 9 + j];
-        const double2 w = blk[(Cc * 16 + B) * 9 + j];
-        uad[j / 3][j % 3] = {v.x, v.y};
-        ucb[j / 3][j % 3] = {w.x, w.y};
-    }
     const double sgn = (((a.neg1 >> A) ^ (a.neg2 >> Cc)) & 1) ? -1.0 : 1.0;
     for (int i0 = 0; i0 < a.n; i0 += NPR_CHUNK) {
         const int m = min(NPR_CHUNK, a.n - i0);
@@ -191,6 +192,47 @@ __global__ __launch_bounds__(256) void k_npr_contract(NprArgs a) {
         if (threadIdx.x == 0)
             for (int s = 0; s < m; ++s) a.out[(long)(i0 + s) * a.g.nz + z] = make_double2(v[2 * s], v[2 * s + 1]);
     }
+}
+
+// From stored path links: thread (A, C) loads U_{A,D} and U_{C,B} from the hypercube's block.
+__global__ __launch_bounds__(256) void k_npr_contract(NprArgs a) {
+    const int z = blockIdx.x;
+    const int A = threadIdx.x >> 4, Cc = threadIdx.x & 15;
+    const int B = A ^ a.d1, D = Cc ^ a.d2;
+    __shared__ double2 fs[NPR_CHUNK][4][16][3];  // the hypercube's field values of a pass
+    C uad[3][3], ucb[3][3];
+    const double2* blk = a.uad + (long)z * 256 * 9;
+#pragma unroll
+    for (int j = 0; j < 9; ++j) {
+        const double2 v = blk[(A * 16 + D) * 9 + j];
+        const double2 w = blk[(Cc * 16 + B) * 9 + j];
+        uad[j / 3][j % 3] = {v.x, v.y};
+        ucb[j / 3][j % 3] = {w.x, w.y};
+    }
+    contract_sets(a, z, uad, ucb, fs);
+}
+
+// Fused: the hypercube's path links are built in LDS (as k_npr_paths does) and contracted at once, so the 36 KB
+// of path links per hypercube never travel to memory and back. Once every thread holds its two matrices the path
+// area is reused for the field staging (a barrier separates the two uses).
+__global__ __launch_bounds__(256) void k_npr_fused(NprArgs a, const double2* __restrict__ U) {
+    const int z = blockIdx.x;
+    const int A = threadIdx.x >> 4, Cc = threadIdx.x & 15;
+    const int B = A ^ a.d1, D = Cc ^ a.d2;
+    __shared__ double2 lk[32][9];
+    __shared__ double2 P[256][9];
+    static_assert(sizeof(double2) * NPR_CHUNK * 4 * 16 * 3 <= sizeof(double2) * 256 * 9, "staging fits the path area");
+    build_paths(a.g, U, z, lk, P);
+    C uad[3][3], ucb[3][3];
+#pragma unroll
+    for (int j = 0; j < 9; ++j) {
+        const double2 v = P[A * 16 + D][j];
+        const double2 w = P[Cc * 16 + B][j];
+        uad[j / 3][j % 3] = {v.x, v.y};
+        ucb[j / 3][j % 3] = {w.x, w.y};
+    }
+    __syncthreads();  // every thread has read its matrices: the path area becomes the field staging
+    contract_sets(a, z, uad, ucb, (double2(*)[4][16][3])&P[0][0]);
 }
 
 // Sign of M_{A, A xor S xor F} = (1/4) tr(gamma_A^dag gamma_S gamma_B gamma_F^dag), B = A xor S xor F.
@@ -238,6 +280,11 @@ hipError_t launch_npr_paths(const Geom& g, const double* links, void* uad, hipSt
 
 hipError_t launch_npr_contract(const Geom& g, const void* uad, int n, const double* const f[4], const int labels[4],
                                double* out, hipStream_t s) {
+    return launch_npr_contract_from(g, uad, nullptr, n, f, labels, out, s);
+}
+
+hipError_t launch_npr_contract_from(const Geom& g, const void* uad, const double* links, int n, const double* const f[4],
+                                    const int labels[4], double* out, hipStream_t s) {
     NprArgs a;
     a.g = npr_geom(g);
     a.uad = (const double2*)uad;
@@ -248,7 +295,8 @@ hipError_t launch_npr_contract(const Geom& g, const void* uad, int n, const doub
     a.d2 = labels[2] ^ labels[3];
     a.neg1 = negative_corners(labels[0], labels[1]);
     a.neg2 = negative_corners(labels[2], labels[3]);
-    hipLaunchKernelGGL(k_npr_contract, dim3(a.g.nz), dim3(256), 0, s, a);
+    if (links) hipLaunchKernelGGL(k_npr_fused, dim3(a.g.nz), dim3(256), 0, s, a, (const double2*)links);
+    else hipLaunchKernelGGL(k_npr_contract, dim3(a.g.nz), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
