@@ -188,6 +188,7 @@ def test_roofline_bytes_match_the_packed_layout():
     assert bench.FLOP_PER_SITE == 8 * (9 * 6 + 6 * 2) + 7 * 6
     assert bench.dslash_bytes_per_site("f32", 12) == 432
     assert bench.iteration_bytes_per_site("f32", 12) == 1032
+    assert bench.iteration_bytes_per_site("f32", 12, "i16") == 648  # 16-bit links, FP32 vectors
 
 
 def test_tune_load_rejects_truncated_and_partial_files(tmp_path):

@@ -1,4 +1,5 @@
-"""GPU NPR contraction (sp_npr_path_links, sp_npr_contract) against the FP64 oracle (oracle/npr.py).
+"""GPU NPR contraction (sp_npr_path_links + sp_npr_contract, and the fused sp_npr_contract_links) against the
+FP64 oracle (oracle/npr.py).
 
 Small lattices are compared whole. On the 20^3x64 workload field, sampled hypercubes are compared with the
 oracle run on the hypercube alone: a hypercube's path links and its O_i(z) depend only on the links and
@@ -40,6 +41,25 @@ def test_npr_matches_oracle(dims, labels):
     assert np.max(np.abs(to_host(uad) - P)) <= 1e-14
     ref = npr.contract(dims, P, *f, *labels)
     assert np.max(np.abs(to_host(O) - ref)) <= 1e-12 * np.max(np.abs(ref))
+    # the fused contraction (path links built in on-chip memory): the same arithmetic in the same order, so the
+    # same bits as the two launches
+    Of = sp.npr_contract_links(lat, to_dev(U), *[to_dev(x) for x in f], labels)
+    assert torch.equal(Of, O)
+
+
+@pytest.mark.parametrize("n", [1, 4, 5, 9])
+def test_npr_fused_field_set_counts(n):
+    """Field-set counts around the staging chunk of four (a partial last chunk, exactly one chunk, several)."""
+    dims = (4, 6, 2, 8)
+    V = li.volume(dims)
+    U = li.near_identity_links(dims, 0.7, 611)
+    f = _fields(n, V, 612 + n)
+    labels = (5, 10, 3, 3)
+    lat = sp.Lattice(dims)
+    Of = to_host(sp.npr_contract_links(lat, to_dev(U), *[to_dev(x) for x in f], labels))
+    ref = npr.contract(dims, npr.path_links(dims, U), *f, *labels)
+    assert Of.shape == ref.shape
+    assert np.max(np.abs(Of - ref)) <= 1e-12 * np.max(np.abs(ref))
 
 
 def test_npr_workload_field_sampled_hypercubes():
@@ -58,6 +78,9 @@ def test_npr_workload_field_sampled_hypercubes():
     small = (2, 2, 2, 2)
     sites = cs[zs]  # corner A of the hypercube is site A of the 2^4 lattice
     uad_s = to_host(uad[torch.as_tensor(zs, device=DEV)])
+    # fused with the path links built on chip: the same bits as the two launches at every hypercube
+    Of = to_host(sp.npr_contract_links(lat, to_dev(U), *[to_dev(x) for x in f], labels))
+    assert np.array_equal(Of, O)
     for k, z in enumerate(zs):
         Us = U[:, sites[k]]
         P = npr.path_links(small, Us)
@@ -74,3 +97,5 @@ def test_npr_errors():
     f = [to_dev(x) for x in _fields(1, V, 606)]
     with pytest.raises(sp.StagError):
         sp.npr_contract(lat, uad, *f, (16, 0, 0, 0))
+    with pytest.raises(sp.StagError):
+        sp.npr_contract_links(lat, to_dev(li.haar_links(dims, 605)), *f, (0, 0, -1, 0))
