@@ -29,7 +29,7 @@ FLOP_PER_SITE = 570  # one half-Dslash output site: 8 SU(3) mat-vecs (66) + 7 co
 # algorithmic bytes per output site of one half-Dslash: 8 links + 1 input vector (perfect neighbour
 # reuse) + 1 output vector
 LINK_BYTES = {("f64", 18): 144, ("f32", 18): 72, ("f32", 12): 48, ("f16", 18): 36, ("f16", 12): 24,
-              ("bf16", 18): 36, ("bf16", 12): 24}
+              ("bf16", 18): 36, ("bf16", 12): 24, ("i16", 18): 36, ("i16", 12): 24}
 VEC_BYTES = {"f64": 48, "f32": 24, "f16": 16, "bf16": 12}
 
 
@@ -109,25 +109,37 @@ def time_dslash(sp, torch, G, prec, inp, out, reps, stream):
     return e0.elapsed_time(e1) / 1e3 / reps
 
 
-def time_flushed(torch, fn, flush, stream, reps=60, trials=5):
+class Flush:
+    """Evicts the Infinity Cache: the library's streaming read kernel over 768 MiB (three times the cache; read,
+    not written, so the cache is left holding no dirty lines whose write-back a following launch would pay)."""
+
+    def __init__(self, sp, torch, dev, nbytes=768 << 20):
+        self.sp = sp
+        self.buf = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+        self.out = torch.empty(self.buf.numel(), dtype=torch.float32, device=dev)
+
+    def __call__(self):
+        self.sp.stream_probe("read", 1, self.buf, self.out)
+
+
+def time_flushed(torch, fn, flush, stream, reps=200, trials=5):
     """Net duration of one launch of fn when the Infinity Cache has been flushed just before it, so that every
     byte comes from HBM: (reps pairs of flush + launch) minus (reps flushes alone), both timed with HIP events
-    on the launch stream, per launch; median over trials. The flush reads a 1 GiB buffer (four times the
-    Infinity Cache; read, not written, so the cache holds no dirty lines whose write-back the launch would pay).
-    Differencing removes the flush and the events' own cost; the launch's start after the flush stays in."""
+    on the launch stream, per launch; median over trials, the two timings interleaved. Differencing removes the
+    flush and the events' own cost; the launch's start after the flush stays in."""
     for _ in range(3):
-        flush.sum()
+        flush()
         fn()
     res = []
     for _ in range(trials):
         f0, f1, e0, e1 = (torch.cuda.Event(enable_timing=True) for _ in range(4))
         f0.record(stream)
         for _ in range(reps):
-            flush.sum()
+            flush()
         f1.record(stream)
         e0.record(stream)
         for _ in range(reps):
-            flush.sum()
+            flush()
             fn()
         e1.record(stream)
         e1.synchronize()
@@ -202,7 +214,7 @@ def stream_ceiling(sp, torch, dev, stream, flush, log, nbytes=2 << 30, small_byt
         b = torch.empty_like(a)
         best = None
         for k in (1, 2, 4, 8):
-            t = time_flushed(torch, lambda: sp.stream_probe("read", k, a, b), flush, stream, reps=30, trials=3)
+            t = time_flushed(torch, lambda: sp.stream_probe("read", k, a, b), flush, stream, reps=100, trials=3)
             gbs = small_bytes / t / 1e9
             if best is None or gbs > best[0]:
                 best = (gbs, k, t)
@@ -217,8 +229,9 @@ KERNEL_SOURCES = ["paper_1511_00088_amd/csrc/sp_device.h", "paper_1511_00088_amd
                   "paper_1511_00088_amd/csrc/sp_launch_dslash.hip", "paper_1511_00088_amd/tune_mi355x.json"]
 
 
-def traffic_file(prec, recon, dims):
-    return os.path.join(ROOT, "profiles", f"dslash_{prec}_r{recon}_{dims[0]}x{dims[1]}x{dims[2]}x{dims[3]}_traffic.md")
+def traffic_file(prec, recon, dims, policy="cached"):
+    return os.path.join(ROOT, "profiles",
+                        f"dslash_{prec}_r{recon}_{policy}_{dims[0]}x{dims[1]}x{dims[2]}x{dims[3]}_traffic.md")
 
 
 def kernel_source_digest():
@@ -231,12 +244,12 @@ def kernel_source_digest():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(prec, recon, dims):
-    """HBM bytes per half-Dslash launch from the committed counter summary, or None when there is none or
-    the kernel sources or the tuning table changed since the counters were taken."""
+def measured_traffic(prec, recon, dims, policy="cached"):
+    """HBM bytes per half-Dslash launch (link loads of the given policy) from the committed counter summary, or
+    None when there is none or the kernel sources or the tuning table changed since the counters were taken."""
     try:
         vals = {}
-        with open(traffic_file(prec, recon, dims)) as f:
+        with open(traffic_file(prec, recon, dims, policy)) as f:
             for line in f:
                 if "=" in line and line.strip().split("=")[0].strip() in ("traffic_bytes_per_launch",
                                                                           "kernel_source_digest"):
@@ -273,9 +286,25 @@ def bench_batched(sp, li, torch, dev, log):
     torch.cuda.synchronize()
     t_s = time.perf_counter() - t0
     ok = all(s.converged for s in st)
+    # algorithmic bytes of one batched iteration: per group of up to four systems sharing a gauge field, the links
+    # of two half operators (t = D_oe p for all of them, then the update) and per system 264 B/site (t = D_oe p:
+    # p in, t out; update: t, p, x and r with x and r read and written; p = r + beta p: r, p in, p out); every
+    # system stays in its group's launches until the batch ends
+    groups = {}
+    for s_ in systems:
+        groups[s_.gauge_index] = groups.get(s_.gauge_index, 0) + 1
+    it_bytes = 0
+    for gi, nsys in groups.items():
+        vh = li.volume(gauges[gi][0]) // 2
+        full, rest = divmod(nsys, 4)
+        for nr in [4] * full + ([rest] if rest else []):
+            it_bytes += vh * (2 * 8 * LINK_BYTES[("f32", 12)] + nr * 264)
+    max_it = max(s.iters for s in st)
     log(f"batched 32 systems: {t_b * 1e3:.1f} ms together, {t_s * 1e3:.1f} ms one by one, all converged={ok}")
     return {"systems": len(sysl), "recon": 12, "s": t_b, "one_by_one_s": t_s, "speedup": t_s / t_b, "all_converged": ok,
-            "max_iters": max(s.iters for s in st), "max_rel_diff_vs_single": err}
+            "max_iters": max_it, "max_rel_diff_vs_single": err, "iteration_bytes": it_bytes,
+            "iteration_us": t_b / max_it * 1e6, "iteration_hbm_frac": it_bytes * max_it / t_b / 1e9 / HBM_PEAK_GBS,
+            "note": "iteration figures over the whole batched solve (set-up, reliable updates, polling included)"}
 
 
 # HYP smearing, algorithmic bytes per lattice site: level 1 reads the 4 input links and writes 12 fields,
@@ -337,6 +366,14 @@ def bench_npr(sp, torch, lat, links, stream, log):
     e1.record(stream)
     e1.synchronize()
     t_c = e0.elapsed_time(e1) / 1e3 / n
+    # fused: the path links built per hypercube on chip inside the contraction
+    sp.npr_contract_links(lat, links, *f, labels)
+    e0.record(stream)
+    for _ in range(n):
+        sp.npr_contract_links(lat, links, *f, labels)
+    e1.record(stream)
+    e1.synchronize()
+    t_f = e0.elapsed_time(e1) / 1e3 / n
     nz = lat.V // 16
     bytes_c = nz * (256 * 144 + NPR_SETS * (4 * 16 * 48 + 16))
     res = {"dims": list(lat.dims), "sets": NPR_SETS, "labels": list(labels), "paths_ms": t_p * 1e3,
@@ -344,8 +381,11 @@ def bench_npr(sp, torch, lat, links, stream, log):
            "contract_bytes": bytes_c, "contract_GBs": bytes_c / t_c / 1e9,
            "contract_hbm_frac": bytes_c / t_c / 1e9 / HBM_PEAK_GBS,
            "paths_bytes": lat.V * 4 * 144 + nz * 256 * 144,
-           "paths_GBs": (lat.V * 4 * 144 + nz * 256 * 144) / t_p / 1e9}
-    log(f"NPR: path links {t_p * 1e3:.3f} ms, contraction of {NPR_SETS} sets {t_c * 1e3:.3f} ms "
+           "paths_GBs": (lat.V * 4 * 144 + nz * 256 * 144) / t_p / 1e9,
+           "fused_ms": t_f * 1e3, "fused_bytes": lat.V * 4 * 144 + nz * NPR_SETS * (4 * 16 * 48 + 16),
+           "fused_GBs": (lat.V * 4 * 144 + nz * NPR_SETS * (4 * 16 * 48 + 16)) / t_f / 1e9,
+           "fused_speedup_vs_two_launches": (t_p + t_c) / t_f}
+    log(f"NPR: path links {t_p * 1e3:.3f} ms, contraction of {NPR_SETS} sets {t_c * 1e3:.3f} ms, fused {t_f * 1e3:.3f} ms "
         f"({res['contract_gflops']:.0f} GFLOP/s, {res['contract_GBs']:.0f} GB/s)")
     return res
 
@@ -405,6 +445,59 @@ def bench_large_lattices(sp, torch, dev, tune_file, log, ws):
         del G, bsrc
     return out
 
+
+def bench_shard_share(sp, torch, dims, links, b, prec, recon, stream, log, ngpu=8):
+    """One GPU's share of the workload cut in time across ngpu GPUs (20^3x8 of 20^3x64), through the shard path
+    the multi-GPU solve would use: pack the two boundary faces, copy each (a device-to-device copy standing in
+    for the transfer to the neighbour), unpack them into the ghost slices, then the half operator on the interior
+    slices and on the boundary slices. HIP events over back-to-back repetitions of each part."""
+    X, Y, Z, T = dims
+    Tl = T // ngpu
+    t0 = (ngpu // 2) * Tl
+    XYZ = X * Y * Z
+    F = XYZ // 2
+    sh = sp.Shard((X, Y, Z, Tl), t0, T)
+    G = sp.Gauge(sh.lat, links[:, t0 * XYZ:(t0 + Tl) * XYZ].contiguous(), lo_prec=prec, recon=recon)
+    ghost = sh.ghost_pack(links[3, (t0 - 1) * XYZ:t0 * XYZ].contiguous(), prec, recon)
+    ext = sh.pack_vec(b[t0 * F:(t0 + Tl) * F].contiguous(), prec)
+    faces = [sh.face_pack(prec, ext, side) for side in (0, 1)]
+    recv = [torch.empty_like(f) for f in faces]
+    out = torch.empty(sh.lat.vec_bytes(prec), dtype=torch.uint8, device=b.device)
+
+    def exchange():
+        for side in (0, 1):
+            sh.face_pack(prec, ext, side, faces[side])
+            recv[side].copy_(faces[side])
+            # the lowest slice becomes the ghost above of the neighbour below, the highest the ghost below of the one
+            # above; here the shard's own faces stand in for its neighbours'
+            sh.face_unpack(prec, recv[side], 1 - side, ext)
+
+    parts = {"exchange": exchange,
+             "interior": lambda: sh.dslash(G, ghost, prec, ext, 1, part=1, out=out),
+             "boundary": lambda: sh.dslash(G, ghost, prec, ext, 1, part=2, out=out),
+             "operator": lambda: sh.dslash(G, ghost, prec, ext, 1, part=0, out=out)}
+    parts["step"] = lambda: (exchange(), parts["interior"](), parts["boundary"]())
+    res = {}
+    for name, fn in parts.items():
+        for _ in range(5):
+            fn()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(100):
+            fn()
+        e1.record(stream)
+        e1.synchronize()
+        res[name + "_us"] = e0.elapsed_time(e1) * 10.0  # ms / 100 repetitions -> us
+    bps = dslash_bytes_per_site(prec, recon)
+    res.update(dims=[X, Y, Z, Tl], t0=t0, face_bytes=sh.face_bytes(prec),
+               operator_hbm_frac=bps * sh.lat.Vh / (res["operator_us"] * 1e-6) / 1e9 / HBM_PEAK_GBS,
+               note=f"one GPU's share of {X}^3x{T} cut in t across {ngpu} GPUs: faces packed, copied on the device "
+                    "(standing in for the transfer) and unpacked; interior and boundary launches")
+    log(f"shard share {res['dims']}: operator {res['operator_us']:.2f} us, exchange {res['exchange_us']:.2f} us, "
+        f"step {res['step_us']:.2f} us")
+    return res
+
 def bench_packing(sp, torch, lat, links, b, inner, recon, stream, log):
     """Packing, done once per gauge field (links) or per source and solution (vectors) and not part of the
     time-to-solution: natural complex128 links to the FP64 recon-18 layout and to the inner precision's
@@ -458,6 +551,8 @@ def main():
     ap.add_argument("--inner", default="f32", choices=["f32", "f16", "bf16"])
     ap.add_argument("--recon", type=int, default=12, choices=[18, 12],
                     help="link storage: 12 = first two rows, third rebuilt as conj(row0 x row1) (exact for SU(3))")
+    ap.add_argument("--links", default=None, choices=["f16", "bf16", "i16"],
+                    help="store the links of the timed solve in 16 bits (FP32 vectors; --inner f32 only)")
     ap.add_argument("--dims", type=int, nargs=4, default=[20, 20, 20, 64])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparator solves")
@@ -466,7 +561,9 @@ def main():
                     help="skip the 16-bit storage solves, the batched workload and the gradient timing")
     ap.add_argument("--tune-file", default=os.path.join(ROOT, "paper_1511_00088_amd", "tune_mi355x.json"),
                     help="tuned launch table to load (tunes in-process when the file is missing)")
-    ap.add_argument("--mode", default="bench", choices=["bench", "traffic", "hyp", "npr"],
+    ap.add_argument("--policy", default="tuned", choices=["tuned", "cached", "streaming"],
+                    help="traffic mode: link loads of the half-Dslash launches (the tuned one, or forced)")
+    ap.add_argument("--mode", default="bench", choices=["bench", "traffic", "hyp", "npr", "large"],
                     help="traffic: only a 1 GiB device copy (counter calibration) and the half-Dslash "
                          "launches, for hardware-counter runs")
     args = ap.parse_args()
@@ -491,7 +588,9 @@ def main():
     lat = sp.Lattice(dims)
     links = torch.from_numpy(c["links"]).to(dev)
     b = torch.from_numpy(c["source"]).to(dev)
-    G = sp.Gauge(lat, links, lo_prec=args.inner, recon=args.recon)
+    if args.links and args.inner != "f32":
+        raise SystemExit("--links needs --inner f32")
+    G = sp.Gauge(lat, links, lo_prec=args.links or args.inner, recon=args.recon)
     G64 = sp.Gauge(lat, links, lo_prec="f64")
     links_cache = [links]
 
@@ -516,16 +615,26 @@ def main():
             dst.copy_(src)
         inp = sp.pack_vec(lat, b, args.inner)
         out = torch.empty_like(inp)
+        key = tune_key(dims, args.inner, args.recon, args.inner)
+        cfg = tuned_entry(args.tune_file, key)
+        if args.policy != "tuned":
+            cfg = dict(cfg, stream=1 if args.policy == "streaming" else 0)
+            pin_launch(sp, key, cfg)
         for _ in range(20):
             sp.dslash_packed(G, args.inner, inp, 1, out)
         torch.cuda.synchronize()
-        print(json.dumps({"mode": "traffic", "copy_bytes": n, "dslash_launches": 20,
+        print(json.dumps({"mode": "traffic", "copy_bytes": n, "dslash_launches": 20, "launch": cfg,
                           "dslash_algorithmic_bytes": dslash_bytes_per_site(args.inner, args.recon) * lat.Vh}))
         return
 
     if args.mode == "npr":
         # the NPR contraction alone (for a kernel trace of its two launches)
         print(json.dumps({"mode": "npr", **bench_npr(sp, torch, lat, G64_links(), stream, log)}))
+        return
+
+    if args.mode == "large":
+        # the 32^3x64 and 28^3x96 solves alone (for a kernel trace of their iterations)
+        print(json.dumps({"mode": "large", **bench_large_lattices(sp, torch, dev, args.tune_file, log, ws)}))
         return
 
     if args.mode == "hyp":
@@ -569,13 +678,14 @@ def main():
     # --- dominant kernel: half-Dslash in the inner precision, HIP events on the launch stream ---
     inp = sp.pack_vec(lat, b, args.inner)
     out = torch.empty_like(inp)
-    bps = dslash_bytes_per_site(args.inner, args.recon)
+    lprec = args.links or args.inner
+    bps = 8 * LINK_BYTES[(lprec, args.recon)] + 2 * VEC_BYTES[args.inner]
     alg_bytes = bps * lat.Vh
-    flush = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+    flush = Flush(sp, torch, dev)
     # both link-load policies of the tuned launch: warm (back-to-back; the 20^3x64 links, 98 MB in FP32
     # recon-12, stay in the Infinity Cache, the solver's situation) and cold (each launch after a 1 GiB read
     # that flushes the Infinity Cache, net of the flush: every byte from HBM, the roofline figure)
-    key = tune_key(dims, args.inner, args.recon, args.inner)
+    key = tune_key(dims, lprec, args.recon, args.inner)
     tuned = tuned_entry(args.tune_file, key)
     policies = {}
     for pol, name in ((0, "cached"), (1, "streaming")):
@@ -617,7 +727,7 @@ def main():
             co = torch.empty_like(ci)
             cb = dslash_bytes_per_site(args.inner, rc)
             tc = time_dslash(sp, torch, Gc, args.inner, ci, co, 100, stream)
-            tcf = time_flushed(torch, lambda: sp.dslash_packed(Gc, args.inner, ci, 1, co), flush, stream, reps=20)
+            tcf = time_flushed(torch, lambda: sp.dslash_packed(Gc, args.inner, ci, 1, co), flush, stream, reps=50)
             ctl[f"{args.inner}_r{rc}"] = {"us": tc * 1e6, "hbm_frac": cb * clat.Vh / tc / 1e9 / HBM_PEAK_GBS,
                                           "flushed_us": tcf * 1e6,
                                           "flushed_hbm_frac": cb * clat.Vh / tcf / 1e9 / HBM_PEAK_GBS}
@@ -629,6 +739,8 @@ def main():
         # every packing at the workload shape, back-to-back (tuned launch of each)
         allc = {}
         for prec, rc in LINK_BYTES:
+            if prec == "i16":  # a link storage only; its operator runs with FP32 vectors (links_16bit_vectors_f32)
+                continue
             Ga = G64 if prec == "f64" else sp.Gauge(lat, G64_links(), lo_prec=prec, recon=rc)
             ai = sp.pack_vec(lat, b, prec)
             ao = torch.empty_like(ai)
@@ -639,26 +751,11 @@ def main():
             del Ga, ai, ao
         dslash_extra["all_packings"] = allc
         log("all packings: " + ", ".join(f"{kk} {vv['us']:.1f} us" for kk, vv in allc.items()))
-        # one GPU's share of the workload cut in t across 8 GPUs: 20^3x8, periodic in t (its own halo)
-        sd = (dims[0], dims[1], dims[2], max(2, dims[3] // 8))
-        slat = sp.Lattice(sd)
-        sl = control_links(sd, 0.3, 52, dev, torch)
-        sv = torch.randn(slat.Vh, 3, dtype=torch.complex128, device=dev)
-        Gs = sp.Gauge(slat, sl, lo_prec=args.inner, recon=args.recon)
-        si = sp.pack_vec(slat, sv, args.inner)
-        so = torch.empty_like(si)
-        ts_ = time_dslash(sp, torch, Gs, args.inner, si, so, 200, stream)
-        face = sd[0] * sd[1] * sd[2] // 2 * VEC_BYTES[args.inner]
-        dslash_extra["shard_share"] = {
-            "dims": list(sd), "us": ts_ * 1e6, "hbm_frac": bps * slat.Vh / ts_ / 1e9 / HBM_PEAK_GBS,
-            "face_bytes": face,
-            "note": "half-Dslash on 1/8 of the workload (t cut in 8), periodic t standing in for the halo; "
-                    "each cut exchanges one face of this size per direction per half-Dslash"}
-        log(f"shard share {sd}: {ts_ * 1e6:.2f} us")
-        del Gs, sl, si, so
+        extra_shard = bench_shard_share(sp, torch, dims, G64_links(), b, args.inner, args.recon, stream, log)
+        dslash_extra["shard_share"] = extra_shard
     del flush
 
-    traffic = measured_traffic(args.inner, args.recon, dims)
+    traffic = measured_traffic(args.inner, args.recon, dims, best_pol)
 
     if not args.no_extras and "err_mixed_vs_fp64_1e12" in extra:
         # 16-bit storage of links and vectors with FP32 arithmetic, same workload
@@ -680,7 +777,7 @@ def main():
         extra["storage_16bit"] = low
         # 16-bit links with FP32 vectors and arithmetic (the links are most of each iteration's bytes)
         l16 = {}
-        for lp in ("f16", "bf16"):
+        for lp in ("i16", "f16", "bf16"):
             for rc in (12, 18):
                 Gl = sp.Gauge(lat, G64_links(), lo_prec=lp, recon=rc)
                 sp.cg_solve(Gl, mass, b, tol=tol, inner="f32", workspace=ws)
@@ -737,7 +834,7 @@ def main():
                "gpu_speedup_mixed": t_cpu / t_mixed}
         log(f"CPU oracle: {t_cpu:.1f} s, {it_cpu} iterations, residual {res_cpu:.2e}")
 
-    ibps = iteration_bytes_per_site(args.inner, args.recon)
+    ibps = iteration_bytes_per_site(args.inner, args.recon, args.links)
     t_it = t_mixed / max(st.iters, 1)
     line = {
         "metric": METRIC,
@@ -756,6 +853,7 @@ def main():
         "config": {"workload": f"even-odd mixed-precision staggered CG, {dims[0]}^3x{dims[3]}, near-identity "
                                f"SU(3) links eps=0.3, m={mass}, Gaussian source, tol={tol}",
                    "dims": list(dims), "mass": mass, "tol": tol, "inner": args.inner, "recon": args.recon,
+                   "links": args.links or args.inner,
                    "reliable_update": "FP64 true residual every 100 iterations or on |r| < 0.1 |r_ru|",
                    "parallelism": "single GPU"},
         "iters": st.iters,
@@ -771,7 +869,8 @@ def main():
                       "note": "whole solve time / iterations (reliable updates, set-up and polling included)"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": f"half-Dslash {args.inner} recon-{args.recon}, {dims[0]}^3x{dims[3]}, {lat.Vh} output sites, "
+                     "kernel": f"half-Dslash {args.inner} vectors, {lprec} recon-{args.recon} links, {dims[0]}^3x{dims[3]}, "
+                               f"{lat.Vh} output sites, "
                                f"{bps} algorithmic B/site",
                      "measured": "each launch after an Infinity Cache flush, net of the flush (HIP events, differencing)",
                      "link_loads": best_pol,
