@@ -160,7 +160,9 @@ int sp_vec_pack(const sp_geom* g, const double* v_nat, int prec, void* out, void
 /* Unpack a packed half vector into natural complex128 [V/2][3]. Asynchronous. */
 int sp_vec_unpack(const sp_geom* g, const void* v, int prec, double* v_nat, void* stream);
 
-/* Half staggered operator: out (parity out_parity) = D_{out_parity, 1-out_parity} in, both packed with
+/* Half staggered operator (the Dslash whose single-precision application dominates the paper's CG, Sec. 3; the
+ * operator is the staggered one of the header above, the paper does not print it):
+ * out (parity out_parity) = D_{out_parity, 1-out_parity} in, both packed with
  * precision prec. Links: U->f64 when prec is SP_F64, else U->lo (U->lo_prec equal to prec, or a 16-bit link
  * storage when prec is SP_F32).
  * Asynchronous on stream. This is the kernel the solver spends most of its time in. */
@@ -171,13 +173,17 @@ int sp_dslash(const sp_geom* g, const sp_gauge* U, int prec, const void* in, voi
  * sp_cg_solve_batched over the same system list. */
 size_t sp_cg_workspace_bytes(int nsys, const sp_system* systems, const sp_cg_params* params);
 
-/* Solve (m^2 - D_eo D_oe) x_e = b_e. b_e, x_e: device natural [V/2][3] complex128. stats: host,
+/* The paper's mixed-precision CG inverter (Sec. 3, "CG Performance"; Fig. 1 and Table 2 time it on 20^3x64): the
+ * iterations in the inner precision, a small double-precision part (true residual, accumulated solution, global
+ * sums) keeping the answer exact. Solve (m^2 - D_eo D_oe) x_e = b_e. b_e, x_e: device natural [V/2][3] complex128. stats: host,
  * nullable. ws: device workspace of at least sp_cg_workspace_bytes bytes. Returns SP_OK,
  * SP_NOT_CONVERGED or an error. Synchronous with respect to stream. */
 int sp_cg_solve(const sp_geom* g, const sp_gauge* U, double mass, const double* b_e, double* x_e,
                 const sp_cg_params* params, sp_cg_stats* stats, void* ws, size_t ws_bytes, void* stream);
 
-/* Solve nsys independent systems together: systems sharing a gauge field and geometry form groups of up
+/* Many solves of the paper's CG (Sec. 3) at once, a batching extension of this library: systems that share a gauge
+ * field share each link load, and independent systems are the unit that spreads over GPUs without communication.
+ * Solve nsys independent systems together: systems sharing a gauge field and geometry form groups of up
  * to 4 right-hand sides; all groups advance in one launch per kernel, captured in a hipGraph per chunk
  * of iterations; converged systems stop updating while the others continue. Groups may differ in volume
  * and time boundary; a zero b_e stops at the first residual check with x_e = 0. stats: host array of nsys
@@ -190,7 +196,9 @@ int sp_cg_solve_batched(int nsys, const sp_system* systems, const sp_cg_params* 
 /* Workspace bytes for sp_cg_force on geometry g. */
 size_t sp_force_workspace_bytes(const sp_geom* g);
 
-/* Adjoint link and mass gradient of a real loss l(x) with x = A^-1 b, given x_e and
+/* Differentiation of the paper's solve (Sec. 3) with respect to the links, the mass and the source, by the adjoint
+ * method (an extension of this library: the paper computes no gradients).
+ * Adjoint link and mass gradient of a real loss l(x) with x = A^-1 b, given x_e and
  * lambda_e = A^-1 (dl/dx) (device natural [V/2][3] complex128), U->f64 packed links:
  *   gamma[4][V][3][3] (device, complex128, overwritten) = dl/dU_mu(n) with the complex convention
  *     dl/dRe U + i dl/dIm U:
@@ -284,7 +292,8 @@ size_t sp_full_workspace_bytes(const sp_geom* g, const sp_gauge* U, const sp_cg_
 int sp_full_solve(const sp_geom* g, const sp_gauge* U, double mass, const double* src, double* psi,
                   const sp_cg_params* params, sp_cg_stats* stats, void* ws, size_t ws_bytes, void* stream);
 
-/* Autotune the half-operator launch (block size, XCD-aware block order) for (g, prec, U->recon) by
+/* Autotune the half-operator launch (block size, XCD-aware block order, and for one right-hand side the
+ * link-load policy: cached or streaming loads) for (g, prec, U->recon) by
  * timing it with HIP events on stream, for one right-hand side and for the 4-right-hand-side operator of
  * batched solves (which has its own register use); in and out are scratch packed vectors of that
  * precision. The 4-right-hand-side timing uses a temporary device buffer of 8 vectors plus descriptors,
@@ -294,7 +303,11 @@ int sp_full_solve(const sp_geom* g, const sp_gauge* U, double mass, const double
 int sp_tune_dslash(const sp_geom* g, const sp_gauge* U, int prec, void* in, void* out, void* stream,
                    double* best_ms);
 
-/* Save / load the tuned launches as JSON text (path on the host file system). Load merges the file's
+/* Save / load the tuned launches as JSON text (path on the host file system). Keys are
+ * "XxYxZxT/l<link prec>/r<recon>/v<vector prec>" (precisions as the SP_* codes), with the suffix "/n4" for the
+ * batched operator and "/solve" for a single solve's iteration (written by the tuning driver, which times short
+ * solves; a single solve uses it when present, else the plain operator's entry). Values are
+ * {"nt": 64|128|256, "remap": 0|1, "stream": 0|1} ("stream" may be left out: 0). Load merges the file's
  * entries into the table; a malformed or truncated file returns SP_ERR_INVALID_ARG and changes nothing. */
 int sp_tune_save(const char* path);
 int sp_tune_load(const char* path);

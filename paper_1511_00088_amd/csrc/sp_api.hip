@@ -190,6 +190,13 @@ LaunchCfg tuned_cfg_batched(const Geom& g, int lp, int recon, int vp) {
     return it == g_tune.end() ? tuned_cfg(g, lp, recon, vp) : it->second;
 }
 
+// Launch shape of a single solve's iteration ("/solve" entry: block order and link-load policy timed on the
+// solver's own launches, by the tuning driver), else the plain operator's.
+LaunchCfg tuned_cfg_solve(const Geom& g, int lp, int recon, int vp) {
+    auto it = g_tune.find(tune_key(g, lp, recon, vp) + "/solve");
+    return it == g_tune.end() ? tuned_cfg(g, lp, recon, vp) : it->second;
+}
+
 // ---------------------------------------------------------------------------------------------------
 // Pinned host staging (control block upload, state polls)
 // ---------------------------------------------------------------------------------------------------
@@ -300,7 +307,7 @@ int make_layout(int nsys, const sp_system* systems, const sp_cg_params* prm, int
         const GroupPlan& G = L->groups[big];
         const int lp = prm->inner == SP_F64 ? SP_F64 : G.U->lo_prec;
         const int rc = prm->inner == SP_F64 ? 18 : G.U->recon;
-        L->cfg = n_rhs_max > 1 ? tuned_cfg_batched(G.g, lp, rc, prm->inner) : tuned_cfg(G.g, lp, rc, prm->inner);
+        L->cfg = n_rhs_max > 1 ? tuned_cfg_batched(G.g, lp, rc, prm->inner) : tuned_cfg_solve(G.g, lp, rc, prm->inner);
         // one system: 256-thread blocks whenever they admit the fused iteration, whose launches have every block
         // sum the partials of all blocks (smaller blocks mean more partials per block); the block order and the
         // link-load policy stay the tuned ones. Measured: FP16 links with 128-thread blocks (the plain operator's
