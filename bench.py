@@ -148,7 +148,7 @@ def time_flushed(torch, fn, flush, stream, reps=200, trials=5):
     return res[len(res) // 2]
 
 
-PREC_CODE = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3}
+PREC_CODE = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3, "i16": 4}
 
 
 def tune_key(dims, lp, recon, vp):
@@ -226,7 +226,8 @@ def stream_ceiling(sp, torch, dev, stream, flush, log, nbytes=2 << 30, small_byt
 
 
 KERNEL_SOURCES = ["paper_1511_00088_amd/csrc/sp_device.h", "paper_1511_00088_amd/csrc/sp_kernels.h",
-                  "paper_1511_00088_amd/csrc/sp_launch_dslash.hip", "paper_1511_00088_amd/tune_mi355x.json"]
+                  "paper_1511_00088_amd/csrc/sp_launch_dslash.hip"]
+TUNE_TABLE = os.path.join(ROOT, "paper_1511_00088_amd", "tune_mi355x.json")
 
 
 def traffic_file(prec, recon, dims, policy="cached"):
@@ -234,19 +235,24 @@ def traffic_file(prec, recon, dims, policy="cached"):
                         f"dslash_{prec}_r{recon}_{policy}_{dims[0]}x{dims[1]}x{dims[2]}x{dims[3]}_traffic.md")
 
 
-def kernel_source_digest():
+def kernel_source_digest(prec, recon, dims, policy):
+    """Hash of the half-Dslash's sources and of the launch shape the counters see (block size and block order
+    of the tuned entry, and the link-load policy): the counter summary holds while this is unchanged."""
     import hashlib
 
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
+    e = tuned_entry(TUNE_TABLE, tune_key(dims, prec, recon, prec))
+    h.update(f"nt={e['nt']} remap={e['remap']} policy={policy}".encode())
     return h.hexdigest()[:16]
 
 
 def measured_traffic(prec, recon, dims, policy="cached"):
     """HBM bytes per half-Dslash launch (link loads of the given policy) from the committed counter summary, or
-    None when there is none or the kernel sources or the tuning table changed since the counters were taken."""
+    None when there is none or the kernel sources or the counted launch shape changed since the counters were
+    taken."""
     try:
         vals = {}
         with open(traffic_file(prec, recon, dims, policy)) as f:
@@ -255,7 +261,7 @@ def measured_traffic(prec, recon, dims, policy="cached"):
                                                                           "kernel_source_digest"):
                     k, v = (x.strip() for x in line.split("=", 1))
                     vals[k] = v
-        if vals.get("kernel_source_digest") != kernel_source_digest():
+        if vals.get("kernel_source_digest") != kernel_source_digest(prec, recon, dims, policy):
             return None
         return float(vals["traffic_bytes_per_launch"])
     except (OSError, KeyError, ValueError):
@@ -477,18 +483,37 @@ def bench_shard_share(sp, torch, dims, links, b, prec, recon, stream, log, ngpu=
              "boundary": lambda: sh.dslash(G, ghost, prec, ext, 1, part=2, out=out),
              "operator": lambda: sh.dslash(G, ghost, prec, ext, 1, part=0, out=out)}
     parts["step"] = lambda: (exchange(), parts["interior"](), parts["boundary"]())
+    parts["step"]()
+    torch.cuda.synchronize()
+    eager = out.clone()
     res = {}
+    # each part is captured REPS times back to back in one graph and the graph replayed, so that neither the rate
+    # of the host's calls (several small launches of a few microseconds each) nor a graph launch's own latency
+    # sets the time
+    REPS, REPLAYS = 50, 10
     for name, fn in parts.items():
-        for _ in range(5):
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
             fn()
+        torch.cuda.current_stream().wait_stream(side)
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            for _ in range(REPS):
+                fn()
+        for _ in range(2):
+            graph.replay()
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record(stream)
-        for _ in range(100):
-            fn()
+        for _ in range(REPLAYS):
+            graph.replay()
         e1.record(stream)
         e1.synchronize()
-        res[name + "_us"] = e0.elapsed_time(e1) * 10.0  # ms / 100 repetitions -> us
+        res[name + "_us"] = e0.elapsed_time(e1) * 1e3 / (REPS * REPLAYS)
+        if name == "step":
+            res["graph_output_equals_eager"] = bool(torch.equal(out, eager))
+        del graph
     bps = dslash_bytes_per_site(prec, recon)
     res.update(dims=[X, Y, Z, Tl], t0=t0, face_bytes=sh.face_bytes(prec),
                operator_hbm_frac=bps * sh.lat.Vh / (res["operator_us"] * 1e-6) / 1e9 / HBM_PEAK_GBS,
@@ -563,7 +588,7 @@ def main():
                     help="tuned launch table to load (tunes in-process when the file is missing)")
     ap.add_argument("--policy", default="tuned", choices=["tuned", "cached", "streaming"],
                     help="traffic mode: link loads of the half-Dslash launches (the tuned one, or forced)")
-    ap.add_argument("--mode", default="bench", choices=["bench", "traffic", "hyp", "npr", "large"],
+    ap.add_argument("--mode", default="bench", choices=["bench", "traffic", "hyp", "npr", "large", "batched", "gradient"],
                     help="traffic: only a 1 GiB device copy (counter calibration) and the half-Dslash "
                          "launches, for hardware-counter runs")
     args = ap.parse_args()
@@ -623,13 +648,25 @@ def main():
         for _ in range(20):
             sp.dslash_packed(G, args.inner, inp, 1, out)
         torch.cuda.synchronize()
+        pol = "streaming" if cfg.get("stream", 0) else "cached"
         print(json.dumps({"mode": "traffic", "copy_bytes": n, "dslash_launches": 20, "launch": cfg,
-                          "dslash_algorithmic_bytes": dslash_bytes_per_site(args.inner, args.recon) * lat.Vh}))
+                          "dslash_algorithmic_bytes": dslash_bytes_per_site(args.inner, args.recon) * lat.Vh,
+                          "kernel_source_digest": kernel_source_digest(args.inner, args.recon, dims, pol)}))
         return
 
     if args.mode == "npr":
         # the NPR contraction alone (for a kernel trace of its two launches)
         print(json.dumps({"mode": "npr", **bench_npr(sp, torch, lat, G64_links(), stream, log)}))
+        return
+
+    if args.mode == "batched":
+        # the 32-system batched workload alone (for a kernel trace of its launches)
+        print(json.dumps({"mode": "batched", **bench_batched(sp, li, torch, dev, log)}))
+        return
+
+    if args.mode == "gradient":
+        # the 16^3x32 forward + adjoint solve + force alone (for a kernel trace)
+        print(json.dumps({"mode": "gradient", **bench_gradient(sp, li, torch, dev, log)}))
         return
 
     if args.mode == "large":

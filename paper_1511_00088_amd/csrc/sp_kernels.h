@@ -130,6 +130,28 @@ __device__ __forceinline__ Rhs<N> rhs_of(const D& d, const GroupDev& G, int gate
     return h;
 }
 
+// This thread's share of the second reduction stage over n block partials of NV arrays: acc[q] += a[q][b] for
+// b = threadIdx.x, + blockDim.x, ... < n, added in increasing b (the order that makes every block of a launch
+// reach the same total, bit for bit). The loads go out eight at a time: a plain loop of dependent adds waits
+// for each load in turn, one memory round trip per partial.
+template <int NV>
+__device__ __forceinline__ void strided_sums(double (&acc)[NV], const double* const (&a)[NV], int n) {
+    constexpr int K = 8;
+    const int nt = blockDim.x;
+    for (int b0 = threadIdx.x; b0 < n; b0 += K * nt) {
+        double v[K][NV];
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+#pragma unroll
+            for (int q = 0; q < NV; ++q) v[j][q] = b0 + j * nt < n ? a[q][b0 + j * nt] : 0.0;
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+#pragma unroll
+            for (int q = 0; q < NV; ++q)
+                if (b0 + j * nt < n) acc[q] += v[j][q];
+    }
+}
+
 // First reduction stage: block totals of NV values per thread, stored by thread 0 as dst[gblk][NV].
 template <int NV>
 __device__ __forceinline__ void block_partials(double* dst, int gblk, double (&v)[NV]) {
@@ -187,10 +209,8 @@ __global__ __launch_bounds__(256) void k_dslash(D d, int p, int in_slot, int out
     static_assert(!FUSED || N == 1, "alpha is formed in-block for one system only");
     double pre[2] = {0.0, 0.0};  // FUSED: this thread's share of the |D_oe p|^2 and |p|^2 partials
     if constexpr (FUSED) {
-        for (int b = threadIdx.x; b < G.nblk; b += blockDim.x) {
-            pre[0] += G.partials[b];
-            pre[1] += G.partials_p[b];
-        }
+        const double* const src[2] = {G.partials, G.partials_p};
+        strided_sums<2>(pre, src, G.nblk);
     }
     const bool live = cb < g.Vh;
     Vec3<R> acc[N];
@@ -466,7 +486,8 @@ __global__ __launch_bounds__(256) void k_xpay_fused(DescSingle d, SolverState* _
     const bool live = cb < Vh;
     // loads that do not depend on the state go first
     double part[1] = {0.0};
-    for (int b = threadIdx.x; b < G.nblk; b += blockDim.x) part[0] += G.partials_r[b];
+    const double* const src[1] = {G.partials_r};
+    strided_sums<1>(part, src, G.nblk);
     Vec3<R> rv = vzero<R>(), pv = vzero<R>();
     if (live) {
         rv = VF::load(d.sys.v[S_R], Vh, cb);
@@ -551,8 +572,10 @@ __global__ __launch_bounds__(256) void k_norm_rec(DescSingle d, SolverState* __r
     }
     const bool direct = (flags & ST_T_STALE) != 0;
     double part[1] = {0.0};
-    if (!direct)
-        for (int b = threadIdx.x; b < G.nblk; b += blockDim.x) part[0] += G.partials_r[b];
+    if (!direct) {
+        const double* const src[1] = {G.partials_r};
+        strided_sums<1>(part, src, G.nblk);
+    }
     Vec3<R> acc = vzero<R>(), told = vzero<R>(), rv = vzero<R>(), pv = vzero<R>();
     if (live) {
         acc = dslash_site<LP, RECON, VP, NT>(g, G.links_lo, direct ? S.v[S_P] : S.v[S_R], 1, site_of(g, 1, cb));
