@@ -6,8 +6,10 @@
 // paths from z_A to z_D of the ordered link products.
 //
 // Two launches, or one fused:
-//  * k_npr_paths: one block per hypercube, one thread per corner pair; the path average is built by the
-//    first-step recursion in LDS (U_mu(x) for a step +mu, U_mu(x - mu)^dag for a step -mu). Output
+//  * k_npr_paths: one block per hypercube; the path average is built by the first-step recursion in LDS
+//    (U_mu(x) for a step +mu, U_mu(x - mu)^dag for a step -mu), one thread per row of a corner pair's matrix,
+//    the 256 matrices held there as nine planes, one per matrix element, with the pairs swizzled across LDS
+//    banks. Output
 //    [nz][256][9] double2: a hypercube's 256 matrices are one contiguous 36 KB block, written and read
 //    whole.
 //  * k_npr_contract: one block per hypercube, one thread per (A, C). M_{AB} is nonzero only for
@@ -16,6 +18,8 @@
 //    NPR_CHUNK field sets are staged in LDS together, and one block reduction gives their O_i(z).
 //  * k_npr_fused: both in one block per hypercube; the path links stay in LDS (for a few field sets per call this
 //    saves the 36 KB per hypercube written by k_npr_paths and read back by k_npr_contract).
+// Every kernel takes its hypercubes in XCD-aware order (block b on XCD b % 8 gets one of a contiguous range), so
+// that neighbouring hypercubes, which share cache lines of the fields and links, meet in one L2.
 // The signs come from the anticommutation relations: gamma_X gamma_Y = (-1)^s(X,Y) gamma_{X xor Y} with
 // s(X,Y) = #{mu > nu : X_mu = Y_nu = 1}, gamma_X^dag = (-1)^{n(n-1)/2} gamma_X for n = |X|, tr gamma_0 = 4.
 #include "sp_launch.h"
@@ -25,7 +29,16 @@ namespace {
 
 using C = Cx<double>;
 
-__device__ __forceinline__ C cmul(C a, C b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+// Every floating-point operation of this file is written out: the compiler fuses nothing by itself
+// (contraction off below), and the products are fused multiply-adds in a fixed order (cmac). The two-launch
+// and the fused contraction inline the same arithmetic, so their results agree bit for bit whatever the
+// surrounding code; left to itself the compiler fuses differently in each kernel.
+#pragma clang fp contract(off)
+
+// acc + a b as four fused multiply-adds
+__device__ __forceinline__ C cmac(C acc, C a, C b) {
+    return {fma(a.re, b.re, fma(-a.im, b.im, acc.re)), fma(a.re, b.im, fma(a.im, b.re, acc.im))};
+}
 
 struct NprGeom {
     int L[4];   // fine extents X, Y, Z, T
@@ -47,27 +60,35 @@ __device__ __forceinline__ void coarse_coords(const NprGeom& g, int z, int* c) {
     c[3] = z / g.Lc[2];
 }
 
-// corner X with bit mu cleared -> index 0..7 of the remaining three bits
-__device__ __forceinline__ int squeeze(int X, int mu) { return (X & ((1 << mu) - 1)) | ((X >> (mu + 1)) << mu); }
-
-__device__ __forceinline__ void mat_ld(const double2* p, C (&m)[3][3], bool dag) {
-#pragma unroll
-    for (int j = 0; j < 9; ++j) {
-        const double2 v = p[j];
-        if (dag) m[j % 3][j / 3] = {v.x, -v.y};
-        else m[j / 3][j % 3] = {v.x, v.y};
-    }
+// Position of the corner pair (X, Y) in a plane of the path area: X * 16 + (Y xor h(X)), with h(X) the product
+// of X and x in GF(16) (modulus x^4 + x + 1). Both h and X -> X xor h(X) are one-to-one, so the pairs that a
+// wavefront touches at once land in distinct LDS banks: (X, Y) for many X and one Y (the contraction), and
+// (X, X xor d) for many X and one corner difference d (the path recursion's reads and writes). The planes are
+// padded to 257 entries, so that one pair's elements in different planes fall in different banks too.
+__device__ __forceinline__ int ppos(int X, int Y) {
+    const int h = ((X << 1) ^ ((X & 8) ? 0x13 : 0)) & 15;
+    return X * 16 + (Y ^ h);
 }
 
-// The path links of hypercube z into P (LDS, pair A * 16 + D), by the 256 threads of a block, one per corner pair
-// (A, D). The average over the k! shortest paths is built from the first step: U_AD = (1/k) sum over the k
-// directions mu in which A and D differ of L(A -> A^mu) U_{A^mu, D}, where L is U_mu(z_A) when A_mu = 0 and
-// U_mu(z_A - mu)^dag otherwise. Pairs are filled in order of k, so every U_{A^mu, D} a thread needs is complete one
-// barrier earlier. lk (LDS) receives the hypercube's 32 links: [mu][corner with bit mu = 0, squeezed]. Ends with a
-// barrier.
-__device__ __forceinline__ void build_paths(const NprGeom& g, const double2* __restrict__ U, int z, double2 (*lk)[9],
-                                            double2 (*P)[9]) {
-    const int t = threadIdx.x, A = t >> 4, D = t & 15;
+// The path area: element j (row j / 3, column j % 3) of the 256 path matrices as nine planes.
+using Paths = double2[9][257];
+
+__device__ __forceinline__ void path_ld(const Paths& P, int X, int Y, C (&m)[3][3]) {
+    const int q = ppos(X, Y);
+#pragma unroll
+    for (int j = 0; j < 9; ++j) m[j / 3][j % 3] = {P[j][q].x, P[j][q].y};
+}
+
+// The path links of hypercube z into P (LDS), by the 256 threads of a block. The average over the k! shortest
+// paths is built from the first step: U_AD = (1/k) sum over the k directions mu in which A and D differ of
+// L(A -> A^mu) U_{A^mu, D}, where L(A -> A^mu) = U_{A, A^mu} is U_mu(z_A) when A_mu = 0 and U_mu(z_A - mu)^dag
+// otherwise. Distance 0 is the identity and distance 1 the hypercube's 32 links and their conjugate transposes,
+// stored straight from memory; pairs at distance 2, 3, 4 follow in that order, so every U_{A^mu, D} and
+// U_{A, A^mu} a thread needs is complete one barrier earlier. A thread forms one pair's average at distances 2
+// and 3 (96 and 64 pairs) and one row of it at distance 4, so that the 16 pairs there, whose averages have the
+// most terms, do not run on 16 threads alone. Ends with a barrier.
+__device__ __forceinline__ void build_paths(const NprGeom& g, const double2* __restrict__ U, int z, Paths& P) {
+    const int t = threadIdx.x;
     int zc[4];
     coarse_coords(g, z, zc);
     for (int e = t; e < 32 * 9; e += 256) {
@@ -75,56 +96,69 @@ __device__ __forceinline__ void build_paths(const NprGeom& g, const double2* __r
         const int X = (c8 & ((1 << mu) - 1)) | ((c8 >> mu) << (mu + 1));  // bit mu = 0
         int c[4];
         for (int nu = 0; nu < 4; ++nu) c[nu] = 2 * zc[nu] + ((X >> nu) & 1);
-        lk[l][j] = U[((long)mu * g.V + lex4(g, c)) * 9 + j];
+        const double2 v = U[((long)mu * g.V + lex4(g, c)) * 9 + j];
+        const int Y = X | (1 << mu);
+        P[j][ppos(X, Y)] = v;                                          // step +mu from z_X
+        P[(j % 3) * 3 + j / 3][ppos(Y, X)] = make_double2(v.x, -v.y);  // step -mu from z_Y: the dagger
     }
-    const int diff = A ^ D, k = __builtin_popcount(diff);
+    if (t < 16)
+#pragma unroll
+        for (int j = 0; j < 9; ++j) P[j][ppos(t, t)] = make_double2(j % 4 == 0 ? 1.0 : 0.0, 0.0);
     __syncthreads();
-    for (int level = 0; level <= 4; ++level) {
-        if (k == level) {
+    for (int level = 2; level <= 4; ++level) {
+        // the corner differences with level bits set, in increasing order, four bits each
+        const int nd = level == 2 ? 6 : level == 3 ? 4 : 1;
+        const unsigned tab = level == 2 ? 0xCA9653u : level == 3 ? 0xEDB7u : 0xFu;
+        const double w = 1.0 / level;
+        // distances 2 and 3: one thread per pair (96 and 64 pairs); distance 4: one thread per row of a pair
+        const int rows = level == 4 ? 3 : 1;
+        if (t < 16 * nd * rows) {
+            const int pr = t % (16 * nd), A = pr / nd, diff = (tab >> (4 * (pr % nd))) & 15, D = A ^ diff;
+            const int r0 = level == 4 ? t / 16 : 0, r1 = level == 4 ? r0 + 1 : 3;
             C acc[3][3];
 #pragma unroll
             for (int i = 0; i < 3; ++i)
 #pragma unroll
-                for (int j = 0; j < 3; ++j) acc[i][j] = {level == 0 && i == j ? 1.0 : 0.0, 0.0};
+                for (int j = 0; j < 3; ++j) acc[i][j] = {0.0, 0.0};
             for (int mu = 0; mu < 4; ++mu) {
                 if (!((diff >> mu) & 1)) continue;
-                const int A1 = A ^ (1 << mu);
-                const bool up = ((A >> mu) & 1) == 0;  // step +mu from z_A, else -mu
-                C L[3][3], R[3][3];
-                mat_ld(lk[mu * 8 + squeeze(up ? A : A1, mu)], L, !up);
-                if (level == 1) {
+                const int A1 = A ^ (1 << mu), ql = ppos(A, A1), qr = ppos(A1, D);
+                C R[3][3];
 #pragma unroll
-                    for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 9; ++j) R[j / 3][j % 3] = {P[j][qr].x, P[j][qr].y};
 #pragma unroll
-                        for (int j = 0; j < 3; ++j) acc[i][j] = L[i][j];
-                    break;
+                for (int i = 0; i < 3; ++i) {
+                    if (i < r0 || i >= r1) continue;
+                    C L[3];
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) L[k] = {P[i * 3 + k][ql].x, P[i * 3 + k][ql].y};
+#pragma unroll
+                    for (int j = 0; j < 3; ++j)
+                        acc[i][j] = cmac(cmac(cmac(acc[i][j], L[0], R[0][j]), L[1], R[1][j]), L[2], R[2][j]);
                 }
-                mat_ld(P[A1 * 16 + D], R, false);
-#pragma unroll
-                for (int i = 0; i < 3; ++i)
-#pragma unroll
-                    for (int j = 0; j < 3; ++j) {
-                        const C a = cmul(L[i][0], R[0][j]), b = cmul(L[i][1], R[1][j]), c = cmul(L[i][2], R[2][j]);
-                        acc[i][j].re += a.re + b.re + c.re;
-                        acc[i][j].im += a.im + b.im + c.im;
-                    }
             }
-            const double w = level > 1 ? 1.0 / level : 1.0;
+            const int q = ppos(A, D);
 #pragma unroll
-            for (int j = 0; j < 9; ++j) P[t][j] = make_double2(w * acc[j / 3][j % 3].re, w * acc[j / 3][j % 3].im);
+            for (int i = 0; i < 3; ++i)
+                if (i >= r0 && i < r1)
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) P[i * 3 + j][q] = make_double2(w * acc[i][j].re, w * acc[i][j].im);
         }
         __syncthreads();
     }
 }
 
-// One block per hypercube: the path links, written as one contiguous 36 KB block per hypercube.
+// One block per hypercube: the path links, written as one contiguous 36 KB block per hypercube (pair A * 16 + D,
+// then the nine elements).
 __global__ __launch_bounds__(256) void k_npr_paths(NprGeom g, const double2* __restrict__ U, double2* __restrict__ out) {
-    __shared__ double2 lk[32][9];
-    __shared__ double2 P[256][9];
-    build_paths(g, U, blockIdx.x, lk, P);
-    double2* o = out + (long)blockIdx.x * 256 * 9;
-    const double2* src = &P[0][0];
-    for (int e = threadIdx.x; e < 256 * 9; e += 256) o[e] = src[e];
+    __shared__ Paths P;
+    const int z = remap_block(blockIdx.x, gridDim.x);
+    build_paths(g, U, z, P);
+    double2* o = out + (long)z * 256 * 9;
+    for (int e = threadIdx.x; e < 256 * 9; e += 256) {
+        const int pair = e / 9, j = e % 9;
+        o[e] = P[j][ppos(pair >> 4, pair & 15)];
+    }
 }
 
 struct NprArgs {
@@ -137,30 +171,59 @@ struct NprArgs {
     unsigned neg1, neg2;                  // bit A set: M_{A, A xor d} = -1
 };
 
-// Field sets per pass of k_npr_contract: their field values are staged together, so a pass pays one load
+// Field sets per pass of the contraction: their field values are staged together, so a pass pays one load
 // latency, and one block reduction covers all of them.
 constexpr int NPR_CHUNK = 4;
+// The 192 field values per set and hypercube (4 fields x 16 corners x 3 colours) of a pass, over 256 threads.
+static_assert(NPR_CHUNK * 192 == 3 * 256, "a pass's field values are three per thread");
+
+// Offset of corner X of a hypercube from its corner 0 in the lattice (no wrap: 2 z_mu + 1 < L_mu).
+__device__ __forceinline__ int corner_offset(const NprGeom& g, int X) {
+    return (X & 1) + g.L[0] * (((X >> 1) & 1) + g.L[1] * (((X >> 2) & 1) + g.L[2] * (X >> 3)));
+}
+
+// Field value q of this thread's share (element threadIdx.x + 256 q) of the pass starting at set i0. The load is
+// always issued: an element past the pass reads the pass's first element instead, and stage_put does not store
+// it (loads under a branch would each wait for their data before the next one).
+__device__ __forceinline__ double2 stage_get(const NprArgs& a, int base, int i0, int q) {
+    const int m = min(NPR_CHUNK, a.n - i0);
+    const int e0 = threadIdx.x + 256 * q, e = e0 < m * 192 ? e0 : 0;
+    const int s = e / 192, r0 = e % 192, fi = r0 / 48, r = r0 % 48, corner = r / 3, c = r % 3;
+    return a.f[fi][((long)(i0 + s) * a.g.V + base + corner_offset(a.g, corner)) * 3 + c];
+}
+
+__device__ __forceinline__ void stage_put(const NprArgs& a, int i0, int q, double2 v, double2 (*fs)[4][16][3]) {
+    const int m = min(NPR_CHUNK, a.n - i0);
+    const int e = threadIdx.x + 256 * q;
+    if (e < m * 192) fs[e / 192][(e % 192) / 48][(e % 48) / 3][e % 3] = v;
+}
+
+// Lattice index of corner 0 of hypercube z.
+__device__ __forceinline__ int npr_base(const NprGeom& g, int z) {
+    int zc[4];
+    coarse_coords(g, z, zc);
+    const int c0[4] = {2 * zc[0], 2 * zc[1], 2 * zc[2], 2 * zc[3]};
+    return lex4(g, c0);
+}
 
 // The contraction of hypercube z for every field set, by thread (A, C) of a block holding U_{A,D} and U_{C,B} in
-// registers; fs (LDS) stages the hypercube's field values of NPR_CHUNK field sets at a time.
-__device__ __forceinline__ void contract_sets(const NprArgs& a, int z, const C (&uad)[3][3], const C (&ucb)[3][3],
-                                              double2 (*fs)[4][16][3]) {
+// registers; fs (LDS) stages the hypercube's field values of NPR_CHUNK field sets at a time. When staged, the
+// caller has put the first pass's values in fs already (loaded early, so that their latency overlaps other
+// work); otherwise, and for later passes, the values are copied one at a time as a pass starts
+// (register staging there, or prefetching across the arithmetic, raises the kernel's registers past three
+// waves per SIMD; staging ahead of the path-link loads of k_npr_contract made it slower).
+__device__ __forceinline__ void contract_sets(const NprArgs& a, int z, int base, const C (&uad)[3][3],
+                                              const C (&ucb)[3][3], double2 (*fs)[4][16][3], bool staged) {
     const int A = threadIdx.x >> 4, Cc = threadIdx.x & 15;
     const int B = A ^ a.d1, D = Cc ^ a.d2;
-    int zc[4];
-    coarse_coords(a.g, z, zc);
-    const int c0[4] = {2 * zc[0], 2 * zc[1], 2 * zc[2], 2 * zc[3]};
-    const int base = lex4(a.g, c0);  // z_0
     const double sgn = (((a.neg1 >> A) ^ (a.neg2 >> Cc)) & 1) ? -1.0 : 1.0;
     for (int i0 = 0; i0 < a.n; i0 += NPR_CHUNK) {
         const int m = min(NPR_CHUNK, a.n - i0);
-        for (int e = threadIdx.x; e < m * 192; e += 256) {
-            const int s = e / 192, r0 = e % 192, fi = r0 / 48, r = r0 % 48, corner = r / 3, c = r % 3;
-            // corner offset of z_corner from z_0 (no wrap: 2 z_mu + 1 < L_mu)
-            const int off = (corner & 1) + a.g.L[0] * (((corner >> 1) & 1) + a.g.L[1] * (((corner >> 2) & 1) +
-                                                                                    a.g.L[2] * (corner >> 3)));
-            fs[s][fi][corner][c] = a.f[fi][((long)(i0 + s) * a.g.V + base + off) * 3 + c];
-        }
+        if (i0 > 0 || !staged)
+            for (int e = threadIdx.x; e < m * 192; e += 256) {
+                const int s = e / 192, r0 = e % 192, fi = r0 / 48, r = r0 % 48, corner = r / 3, c = r % 3;
+                fs[s][fi][corner][c] = a.f[fi][((long)(i0 + s) * a.g.V + base + corner_offset(a.g, corner)) * 3 + c];
+            }
         __syncthreads();
         double v[2 * NPR_CHUNK];
 #pragma unroll
@@ -175,31 +238,32 @@ __device__ __forceinline__ void contract_sets(const NprArgs& a, int z, const C (
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     const double2 x4 = fs[s][3][D][c], x2 = fs[s][1][B][c];
-                    const C p = cmul(uad[r][c], {x4.x, x4.y}), q = cmul(ucb[r][c], {x2.x, x2.y});
-                    s1 = {s1.re + p.re, s1.im + p.im};
-                    s2 = {s2.re + q.re, s2.im + q.im};
+                    s1 = cmac(s1, uad[r][c], {x4.x, x4.y});
+                    s2 = cmac(s2, ucb[r][c], {x2.x, x2.y});
                 }
                 const double2 y1 = fs[s][0][A][r], y3 = fs[s][2][Cc][r];
-                const C p = cmul({y1.x, y1.y}, s1), q = cmul({y3.x, y3.y}, s2);
-                b1 = {b1.re + p.re, b1.im + p.im};
-                b2 = {b2.re + q.re, b2.im + q.im};
+                b1 = cmac(b1, {y1.x, y1.y}, s1);
+                b2 = cmac(b2, {y3.x, y3.y}, s2);
             }
-            const C term = cmul(b1, b2);
+            const C term = cmac({0.0, 0.0}, b1, b2);
             v[2 * s] = sgn * term.re;
             v[2 * s + 1] = sgn * term.im;
         }
         block_sum<2 * NPR_CHUNK>(v);  // ends with a barrier, so the staged values can be replaced next
         if (threadIdx.x == 0)
-            for (int s = 0; s < m; ++s) a.out[(long)(i0 + s) * a.g.nz + z] = make_double2(v[2 * s], v[2 * s + 1]);
+#pragma unroll
+            for (int s = 0; s < NPR_CHUNK; ++s)
+                if (s < m) a.out[(long)(i0 + s) * a.g.nz + z] = make_double2(v[2 * s], v[2 * s + 1]);
     }
 }
 
 // From stored path links: thread (A, C) loads U_{A,D} and U_{C,B} from the hypercube's block.
 __global__ __launch_bounds__(256) void k_npr_contract(NprArgs a) {
-    const int z = blockIdx.x;
+    const int z = remap_block(blockIdx.x, gridDim.x);
     const int A = threadIdx.x >> 4, Cc = threadIdx.x & 15;
     const int B = A ^ a.d1, D = Cc ^ a.d2;
     __shared__ double2 fs[NPR_CHUNK][4][16][3];  // the hypercube's field values of a pass
+    const int base = npr_base(a.g, z);
     C uad[3][3], ucb[3][3];
     const double2* blk = a.uad + (long)z * 256 * 9;
 #pragma unroll
@@ -209,30 +273,31 @@ __global__ __launch_bounds__(256) void k_npr_contract(NprArgs a) {
         uad[j / 3][j % 3] = {v.x, v.y};
         ucb[j / 3][j % 3] = {w.x, w.y};
     }
-    contract_sets(a, z, uad, ucb, fs);
+    contract_sets(a, z, base, uad, ucb, fs, false);
 }
 
 // Fused: the hypercube's path links are built in LDS (as k_npr_paths does) and contracted at once, so the 36 KB
-// of path links per hypercube never travel to memory and back. Once every thread holds its two matrices the path
-// area is reused for the field staging (a barrier separates the two uses).
+// of path links per hypercube never travel to memory and back. The first pass's field values are loaded before
+// the paths are built; once every thread holds its two matrices the path area is reused for the field staging
+// (a barrier separates the two uses).
 __global__ __launch_bounds__(256) void k_npr_fused(NprArgs a, const double2* __restrict__ U) {
-    const int z = blockIdx.x;
+    const int z = remap_block(blockIdx.x, gridDim.x);
     const int A = threadIdx.x >> 4, Cc = threadIdx.x & 15;
     const int B = A ^ a.d1, D = Cc ^ a.d2;
-    __shared__ double2 lk[32][9];
-    __shared__ double2 P[256][9];
-    static_assert(sizeof(double2) * NPR_CHUNK * 4 * 16 * 3 <= sizeof(double2) * 256 * 9, "staging fits the path area");
-    build_paths(a.g, U, z, lk, P);
+    __shared__ Paths P;
+    static_assert(sizeof(double2) * NPR_CHUNK * 4 * 16 * 3 <= sizeof(Paths), "staging fits the path area");
+    const int base = npr_base(a.g, z);
+    const double2 f0 = stage_get(a, base, 0, 0), f1 = stage_get(a, base, 0, 1), f2 = stage_get(a, base, 0, 2);
+    build_paths(a.g, U, z, P);
     C uad[3][3], ucb[3][3];
-#pragma unroll
-    for (int j = 0; j < 9; ++j) {
-        const double2 v = P[A * 16 + D][j];
-        const double2 w = P[Cc * 16 + B][j];
-        uad[j / 3][j % 3] = {v.x, v.y};
-        ucb[j / 3][j % 3] = {w.x, w.y};
-    }
+    path_ld(P, A, D, uad);
+    path_ld(P, Cc, B, ucb);
     __syncthreads();  // every thread has read its matrices: the path area becomes the field staging
-    contract_sets(a, z, uad, ucb, (double2(*)[4][16][3])&P[0][0]);
+    double2(*fs)[4][16][3] = (double2(*)[4][16][3])&P[0][0];
+    stage_put(a, 0, 0, f0, fs);
+    stage_put(a, 0, 1, f1, fs);
+    stage_put(a, 0, 2, f2, fs);
+    contract_sets(a, z, base, uad, ucb, fs, true);
 }
 
 // Sign of M_{A, A xor S xor F} = (1/4) tr(gamma_A^dag gamma_S gamma_B gamma_F^dag), B = A xor S xor F.
