@@ -23,6 +23,7 @@
 // The signs come from the anticommutation relations: gamma_X gamma_Y = (-1)^s(X,Y) gamma_{X xor Y} with
 // s(X,Y) = #{mu > nu : X_mu = Y_nu = 1}, gamma_X^dag = (-1)^{n(n-1)/2} gamma_X for n = |X|, tr gamma_0 = 4.
 #include "sp_launch.h"
+#include "sp_npr_layout.h"
 
 namespace sp {
 namespace {
@@ -60,18 +61,9 @@ __device__ __forceinline__ void coarse_coords(const NprGeom& g, int z, int* c) {
     c[3] = z / g.Lc[2];
 }
 
-// Position of the corner pair (X, Y) in a plane of the path area: X * 16 + (Y xor h(X)), with h(X) the product
-// of X and x in GF(16) (modulus x^4 + x + 1). Both h and X -> X xor h(X) are one-to-one, so the pairs that a
-// wavefront touches at once land in distinct LDS banks: (X, Y) for many X and one Y (the contraction), and
-// (X, X xor d) for many X and one corner difference d (the path recursion's reads and writes). The planes are
-// padded to 257 entries, so that one pair's elements in different planes fall in different banks too.
-__device__ __forceinline__ int ppos(int X, int Y) {
-    const int h = ((X << 1) ^ ((X & 8) ? 0x13 : 0)) & 15;
-    return X * 16 + (Y ^ h);
-}
-
-// The path area: element j (row j / 3, column j % 3) of the 256 path matrices as nine planes.
-using Paths = double2[9][257];
+// The path area: element j (row j / 3, column j % 3) of the 256 path matrices as nine planes, pair (X, Y) at
+// ppos(X, Y) in each (sp_npr_layout.h).
+using Paths = double2[9][NPR_PLANE];
 
 __device__ __forceinline__ void path_ld(const Paths& P, int X, int Y, C (&m)[3][3]) {
     const int q = ppos(X, Y);
