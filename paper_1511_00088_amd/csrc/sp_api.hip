@@ -458,15 +458,16 @@ hipError_t enqueue_reliable(const D& d, const Plan& pl, bool accum_done, hipStre
     return launch_xpay(d, pl.nblocks, pl.cfg, pl.inner, G_XPAY, s);
 }
 
-// Start of a solve: |b|^2; r = b - A x0 in FP64; p = r.
+// Start of a solve: |b|^2; r = b - A x0 in FP64 (r = b when there is no x0: no operator); p = r.
 template <class D>
-hipError_t enqueue_setup(const D& d, const Plan& pl, hipStream_t s) {
+hipError_t enqueue_setup(const D& d, const Plan& pl, bool zero_x0, hipStream_t s) {
     hipError_t e;
     if ((e = launch_norm_b(d, pl.nblocks, pl.cfg, s))) return e;
     if ((e = launch_finalize(d, pl.ngroups, FIN_NORM_B, G_ALIVE, s))) return e;
-    if ((e = launch_dslash(d, pl.nblocks, pl.cfg, SP_F64, 18, SP_F64, 1, S_X64, S_T64, DS_PLAIN, G_ALIVE, 1, s)))
+    if (!zero_x0 &&
+        (e = launch_dslash(d, pl.nblocks, pl.cfg, SP_F64, 18, SP_F64, 1, S_X64, S_T64, DS_PLAIN, G_ALIVE, 1, s)))
         return e;
-    if ((e = launch_resid(d, pl.nblocks, pl.cfg, pl.inner, 1, s))) return e;
+    if ((e = launch_resid(d, pl.nblocks, pl.cfg, pl.inner, zero_x0 ? 2 : 1, s))) return e;
     if ((e = launch_finalize(d, pl.ngroups, FIN_RESID_INIT, G_ALIVE, s))) return e;
     return launch_xpay(d, pl.nblocks, pl.cfg, pl.inner, G_XPAY, s);
 }
@@ -684,7 +685,10 @@ int solve_impl(int nsys, const sp_system* systems, const sp_cg_params* prm, sp_c
         db.sys = (const SysDev*)(base + L.sdesc_off);
         db.ngroups = (int)L.groups.size();
     }
-    auto setup = [&]() { return batched ? enqueue_setup(db, pl, stream) : enqueue_setup(ds, pl, stream); };
+    const bool zero_x0 = !prm->use_x0;
+    auto setup = [&]() {
+        return batched ? enqueue_setup(db, pl, zero_x0, stream) : enqueue_setup(ds, pl, zero_x0, stream);
+    };
     HIP_TRY(setup());
 
     hipGraphExec_t exec = nullptr;

@@ -337,7 +337,9 @@ __global__ __launch_bounds__(256) void k_dslash(D d, int p, int in_slot, int out
 
 // ------------------------------------------------------------------------------------------------------
 // FP64 true residual on even sites: r = b - m^2 x + D_eo t64, t64 = D_oe x (previous launch).
-// Writes R (inner precision OP); block partials of |r|^2 and Re<r, p> (p unused when init).
+// Writes R (inner precision OP); block partials of |r|^2 and Re<r, p> (p unused when init). init: 0 a reliable
+// update, 1 the start of a solve from a given x0, 2 the start from x0 = 0, where r = b needs no operator (t64 is
+// then neither read nor needed).
 // ------------------------------------------------------------------------------------------------------
 template <int OP, int N, class D>
 __global__ __launch_bounds__(256) void k_resid(D d, int init, int remap) {
@@ -355,6 +357,7 @@ __global__ __launch_bounds__(256) void k_resid(D d, int init, int remap) {
     double dots[2 * N];
 #pragma unroll
     for (int r = 0; r < 2 * N; ++r) dots[r] = 0.0;
+    const bool zero_x = init == 2;
     if (cb < g.Vh) {
         const Site s = site_of(g, 0, cb);
         Vec3<double> acc[N];
@@ -364,8 +367,11 @@ __global__ __launch_bounds__(256) void k_resid(D d, int init, int remap) {
             acc[r] = vzero<double>();
             tin[r] = h.act[r] ? sys_of(d, G.sys0 + r).v[S_T64] : nullptr;
         }
-#pragma unroll
-        for (int mu = 0; mu < 4; ++mu) {
+        // two directions at a time for one system, as in the FP64 half operator (all four put the kernel past 256
+        // registers, one wave per SIMD)
+        constexpr int UNROLL = N == 1 ? 2 : 4;
+#pragma unroll UNROLL
+        for (int mu = 0; mu < (zero_x ? 0 : 4); ++mu) {
             double e = (double)eta_sign(s, mu);
             double sf = e, sb = -e;
             if (mu == 3 && g.bc_t) {
@@ -388,7 +394,7 @@ __global__ __launch_bounds__(256) void k_resid(D d, int init, int remap) {
             if (!h.act[r]) continue;
             const SysDev& S = sys_of(d, G.sys0 + r);
             const Vec3<double> b = VecFmt<F64>::load(S.v[S_B64], g.Vh, cb);
-            const Vec3<double> x = VecFmt<F64>::load(S.v[S_X64], g.Vh, cb);
+            const Vec3<double> x = zero_x ? vzero<double>() : VecFmt<F64>::load(S.v[S_X64], g.Vh, cb);
             const double m2 = h.st[r]->m2;
             Vec3<RO> ro, pv;
             if (!init) pv = VO::load(S.v[S_P], g.Vh, cb);
