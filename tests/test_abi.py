@@ -143,16 +143,39 @@ def test_tune_cache_roundtrip(tmp_path):
     p = tmp_path / "tune.json"
     # the second entry has the form tables took before the link-load policy ("stream") existed: cached loads
     p.write_text('{\n  "20x20x20x64/l1/r18/v1": {"nt": 128, "remap": 1, "stream": 1},\n'
-                 '  "20x20x20x64/l1/r18/v1/n4": {"nt": 256, "remap": 0}\n}\n')
+                 '  "20x20x20x64/l1/r18/v1/n4": {"nt": 256, "remap": 0},\n'
+                 '  "20x20x20x64/l1/r18/v1/solve": {"nt": 256, "remap": 1, "stream": 1}\n}\n')
     assert lib.sp_tune_load(str(p).encode()) == 0
     q = tmp_path / "out.json"
     assert lib.sp_tune_save(str(q).encode()) == 0
     assert '"20x20x20x64/l1/r18/v1": {"nt": 128, "remap": 1, "stream": 1}' in q.read_text()
     assert '"20x20x20x64/l1/r18/v1/n4": {"nt": 256, "remap": 0, "stream": 0}' in q.read_text()
+    assert '"20x20x20x64/l1/r18/v1/solve": {"nt": 256, "remap": 1, "stream": 1}' in q.read_text()
     p.write_text('{"x": {"nt": 128, "remap": 1, "strem": 1}}')
     assert lib.sp_tune_load(str(p).encode()) == _lib.SP_ERR_INVALID_ARG
     p.write_text('{"x": {"nt": 100, "remap": 1}}')
     assert lib.sp_tune_load(str(p).encode()) == _lib.SP_ERR_INVALID_ARG
+    lib.sp_release_cache()
+
+
+def test_shipped_tune_table_loads_and_covers_the_workloads():
+    """The committed MI355X table passes the strict reader and holds, for the benchmark's lattices, the plain
+    operator's entry, the batched operator's ("/n4") and the single solve's ("/solve", timed on solves)."""
+    import json
+    import os
+
+    lib = _lib.load()
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1511_00088_amd",
+                        "tune_mi355x.json")
+    assert lib.sp_tune_load(path.encode()) == 0
+    with open(path) as f:
+        table = json.load(f)
+    for key in ("20x20x20x64/l1/r12/v1", "20x20x20x64/l1/r12/v1/n4", "20x20x20x64/l1/r12/v1/solve",
+                "20x20x20x64/l4/r12/v1/solve", "20x20x20x64/l0/r18/v0/solve", "32x32x32x64/l1/r12/v1/solve",
+                "28x28x28x96/l1/r12/v1/solve"):
+        assert key in table, key
+        assert table[key]["nt"] in (64, 128, 256) and table[key]["remap"] in (0, 1)
+        assert table[key].get("stream", 0) in (0, 1)
     lib.sp_release_cache()
 
 
