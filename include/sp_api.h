@@ -95,7 +95,8 @@ typedef struct {
  *  ru_every   reliable update at least every ru_every iterations (ignored for SP_F64; <= 0 picks 100, or
  *             50 for FP32 iterations on SP_I16 links; checked at the end of each poll chunk)
  *  poll_chunk iterations per device-side chunk (one hipGraph launch) between host convergence polls
- *             (<= 0 picks 25)
+ *             (<= 0 picks 100 for a single solve with FP32 iterations on FP32 links, or SP_F64, of at least
+ *             2^16 even sites; 25 otherwise)
  *  use_x0     1: x_e holds the initial guess on entry; 0: start from zero
  *  use_graph  1: capture each chunk in a hipGraph and replay it; 0: launch kernels one by one
  * A reliable update also runs whenever the iterated residual reaches tol, at the iteration cap, and (for

@@ -208,7 +208,8 @@ struct Pinned {
         if (p) (void)hipHostFree(p);
         p = nullptr;
         n = 0;
-        hipError_t e = hipHostMalloc(&p, bytes, hipHostMallocDefault);
+        // coherent: the poll slots are written by a kernel (the last node of a chunk's graph) and read by the host
+        hipError_t e = hipHostMalloc(&p, bytes, hipHostMallocCoherent);
         if (e == hipSuccess) n = bytes;
         return e;
     }
@@ -493,10 +494,14 @@ hipStream_t g_capture_stream = nullptr;
 int g_capture_device = -1;
 
 template <class D>
-std::string graph_key(const D& d, const Plan& pl, int iters) {
+std::string graph_key(const D& d, const Plan& pl, int iters, const SolverState* states, SolverState* publish,
+                      int nsys) {
     std::string k((const char*)&d, sizeof d);
     k.append((const char*)&pl, sizeof pl);
     k.append((const char*)&iters, sizeof iters);
+    k.append((const char*)&states, sizeof states);
+    k.append((const char*)&publish, sizeof publish);
+    k.append((const char*)&nsys, sizeof nsys);
     int dev = 0;
     (void)hipGetDevice(&dev);
     k.append((const char*)&dev, sizeof dev);
@@ -505,9 +510,12 @@ std::string graph_key(const D& d, const Plan& pl, int iters) {
 
 void release_graphs();
 
+// The graph of one chunk: its iterations, then the systems' states copied to `publish` (pinned host memory the
+// host polls), so that no separate copy, with its own submission gap, follows each chunk.
 template <class D>
-hipError_t chunk_graph(const D& d, const Plan& pl, int iters, hipGraphExec_t* out) {
-    const std::string key = graph_key(d, pl, iters);
+hipError_t chunk_graph(const D& d, const Plan& pl, int iters, const SolverState* states, SolverState* publish,
+                       int nsys, hipGraphExec_t* out) {
+    const std::string key = graph_key(d, pl, iters, states, publish, nsys);
     auto it = g_graphs.find(key);
     if (it != g_graphs.end()) {
         *out = it->second;
@@ -524,6 +532,7 @@ hipError_t chunk_graph(const D& d, const Plan& pl, int iters, hipGraphExec_t* ou
     }
     if ((e = hipStreamBeginCapture(g_capture_stream, hipStreamCaptureModeThreadLocal))) return e;
     hipError_t ee = enqueue_chunk(d, pl, iters, g_capture_stream);
+    if (!ee) ee = launch_state_publish(states, publish, nsys, g_capture_stream);
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(g_capture_stream, &graph);
     if (ee) {
@@ -669,7 +678,17 @@ int solve_impl(int nsys, const sp_system* systems, const sp_cg_params* prm, sp_c
     pl.ngroups = (int)L.groups.size();
     pl.cfg = L.cfg;
 
-    const int chunk = prm->poll_chunk > 0 ? prm->poll_chunk : 25;
+    // Iterations per chunk, when the caller leaves it: 100 for a single solve with FP32 iterations on FP32 links
+    // (or plain FP64 CG) of at least 2^16 even sites, where each chunk boundary costs a graph launch and a state
+    // poll (about 17 us) and the t recurrence and the kept direction need no earlier reset (20^3x64: 499
+    // iterations at any length from 20 to 100, 23.7 -> 23.4 ms); 25 otherwise: with 16-bit links or vectors the
+    // reliable-update triggers, checked at chunk ends, set the iteration count (fixed-point links: 502 iterations
+    // with 25, 523-760 with 32-64), and small or batched solves keep the finer polling.
+    int chunk = prm->poll_chunk;
+    if (chunk <= 0) {
+        const bool full_links = pl.inner == SP_F64 || (pl.inner == SP_F32 && pl.lp == SP_F32);
+        chunk = (!batched && full_links && L.groups[0].g.Vh >= (1 << 16)) ? 100 : 25;
+    }
     HIP_TRY(g_poll.ensure(2 * sizeof(SolverState) * nsys));
     SolverState* slots[2] = {(SolverState*)g_poll.p, (SolverState*)g_poll.p + nsys};
 
@@ -691,10 +710,15 @@ int solve_impl(int nsys, const sp_system* systems, const sp_cg_params* prm, sp_c
     };
     HIP_TRY(setup());
 
-    hipGraphExec_t exec = nullptr;
+    // with graphs, one per poll slot: each ends by copying the states into its slot
+    const SolverState* dev_states = (const SolverState*)(base + L.states_off);
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
     if (prm->use_graph) {
-        hipError_t e = batched ? chunk_graph(db, pl, chunk, &exec) : chunk_graph(ds, pl, chunk, &exec);
-        HIP_TRY(e);
+        for (int k = 0; k < 2; ++k) {
+            hipError_t e = batched ? chunk_graph(db, pl, chunk, dev_states, slots[k], nsys, &exec[k])
+                                   : chunk_graph(ds, pl, chunk, dev_states, slots[k], nsys, &exec[k]);
+            HIP_TRY(e);
+        }
     }
     Events ev;
     HIP_TRY(ev.create());
@@ -724,11 +748,14 @@ int solve_impl(int nsys, const sp_system* systems, const sp_cg_params* prm, sp_c
             char cr[48];
             snprintf(cr, sizeof cr, "chunk %ld", c);
             const TraceRange chunk_range(cr);
-            if (exec) HIP_TRY(hipGraphLaunch(exec, stream));
-            else HIP_TRY(batched ? enqueue_chunk(db, pl, chunk, stream) : enqueue_chunk(ds, pl, chunk, stream));
+            if (exec[c & 1]) {
+                HIP_TRY(hipGraphLaunch(exec[c & 1], stream));
+            } else {
+                HIP_TRY(batched ? enqueue_chunk(db, pl, chunk, stream) : enqueue_chunk(ds, pl, chunk, stream));
+                HIP_TRY(hipMemcpyAsync(slots[c & 1], dev_states, sizeof(SolverState) * nsys, hipMemcpyDeviceToHost,
+                                       stream));
+            }
         }
-        HIP_TRY(hipMemcpyAsync(slots[c & 1], base + L.states_off, sizeof(SolverState) * nsys, hipMemcpyDeviceToHost,
-                               stream));
         HIP_TRY(hipEventRecord(ev.e[c & 1], stream));
         if (c > max_chunks) {
             // cannot happen unless the device state is corrupted: every system stops at max_iter

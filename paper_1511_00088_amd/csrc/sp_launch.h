@@ -41,6 +41,7 @@ hipError_t launch_norm_b(const D& d, int nblocks, LaunchCfg c, hipStream_t s);
 hipError_t launch_xpay_fused(const DescSingle& d, SolverState* st_out, int chunk_end, int nblocks, LaunchCfg c, int vp,
                              hipStream_t s);
 hipError_t launch_state_copy(const SolverState* src, SolverState* dst, hipStream_t s);
+hipError_t launch_state_publish(const SolverState* src, SolverState* dst, int n, hipStream_t s);
 // First launch of the two-launch iteration of one system in FP32 or FP64 (k_norm_rec).
 hipError_t launch_norm_rec(const DescSingle& d, SolverState* st_out, int nblocks, LaunchCfg c, int lp, int recon, int vp,
                            hipStream_t s);

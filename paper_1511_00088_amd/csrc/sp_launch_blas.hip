@@ -14,6 +14,13 @@ __global__ void k_state_copy(const SolverState* __restrict__ src, SolverState* _
     if (threadIdx.x == 0) *dst = *src;
 }
 
+// dst[0..n) = src[0..n), one block: the systems' states copied to the pinned host buffer that the solver polls,
+// as the last node of a chunk's graph (in 16-byte words; the state's size is a multiple of 64 bytes).
+__global__ __launch_bounds__(256) void k_state_publish(const uint4* __restrict__ src, uint4* __restrict__ dst, int words) {
+    for (int i = threadIdx.x; i < words; i += blockDim.x) dst[i] = src[i];
+}
+static_assert(sizeof(SolverState) % sizeof(uint4) == 0, "states copy as 16-byte words");
+
 template <class D>
 struct NOf {
     static constexpr int value = NB;
@@ -52,6 +59,12 @@ hipError_t launch_xpay_fused(const DescSingle& d, SolverState* st_out, int chunk
     if (vp == BF16) SP_LAUNCH(BF16);
 #undef SP_LAUNCH
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_state_publish(const SolverState* src, SolverState* dst, int n, hipStream_t s) {
+    const int words = (int)(n * sizeof(SolverState) / sizeof(uint4));
+    hipLaunchKernelGGL(k_state_publish, dim3(1), dim3(256), 0, s, (const uint4*)src, (uint4*)dst, words);
+    return hipGetLastError();
 }
 
 hipError_t launch_state_copy(const SolverState* src, SolverState* dst, hipStream_t s) {
