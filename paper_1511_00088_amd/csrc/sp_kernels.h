@@ -219,10 +219,11 @@ __global__ __launch_bounds__(256) void k_dslash(D d, int p, int in_slot, int out
 
     if (live) {
         const Site s = site_of(g, p, cb);
-// one direction at a time for several systems (their gathers would not fit in registers otherwise); two at
-// a time in FP64, where all four put 384 values in flight and leave one wave per SIMD, and for FP32
-// recon-12, whose row rebuild makes four at a time cost 125-136 VGPRs (measured 3-4% slower)
-        constexpr int UNROLL = N == 1 ? unroll_dirs(LP, RECON, VP, NT) : 1;
+// several systems: two directions at a time (FP32 and 16-bit vectors; 105-158 VGPRs for four systems, 1% faster
+// batches than one at a time), one in FP64 (its four-system update holds 216 VGPRs already); one system: two at a time
+// in FP64, where all four put 384 values in flight and leave one wave per SIMD, and for FP32 recon-12 with
+// cached link loads, whose row rebuild makes four at a time cost 125-136 VGPRs (measured 3-4% slower)
+        constexpr int UNROLL = N == 1 ? unroll_dirs(LP, RECON, VP, NT) : (VP == F64 ? 1 : 2);
 #pragma unroll UNROLL
         for (int mu = 0; mu < 4; ++mu) {
             R e = (R)eta_sign(s, mu);
