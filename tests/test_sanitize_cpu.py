@@ -1,6 +1,6 @@
 """CPU builds with AddressSanitizer and UndefinedBehaviorSanitizer of the oracle (gcc) and of the library's
 host-side ABI glue (hipcc, sanitizers on the host code only), each driven through every entry point that runs
-without a GPU (tests/oracle_sanitize.c, tests/abi_sanitize.cpp). A sanitizer report aborts the driver."""
+without a GPU (tests/oracle_sanitize.c, tests/abi_sanitize.cpp). A sanitizer report aborts the test program."""
 import glob
 import os
 import shutil
