@@ -41,9 +41,11 @@ def iteration_bytes_per_site(prec, recon, link_prec=None):
     """Algorithmic bytes per even site of one mixed-precision CG iteration. FP32 (and FP64) iterations take two
     launches: t = D_oe r + beta t with p = r + beta p (links, r, t read and written, p read and written) and
     x += alpha p, r -= alpha (m^2 p - D_eo t) (links, t, p, x and r read and written); x is FP32 for every
-    inner precision. 16-bit vector storage takes three: t = D_oe p, the same update, p = r + beta p.
-    link_prec: the links' storage precision when it differs from the vectors' (16-bit links, FP32 vectors)."""
-    links, v, x = 8 * LINK_BYTES[(link_prec or prec, recon)], VEC_BYTES[prec], VEC_BYTES["f32"]
+    inner precision (FP64 for plain FP64 CG). 16-bit vector storage takes three: t = D_oe p, the same update,
+    p = r + beta p. link_prec: the links' storage precision when it differs from the vectors' (16-bit links,
+    FP32 vectors)."""
+    links, v = 8 * LINK_BYTES[(link_prec or prec, recon)], VEC_BYTES[prec]
+    x = VEC_BYTES["f64"] if prec == "f64" else VEC_BYTES["f32"]
     if prec in ("f32", "f64"):
         return (links + v + 2 * v + 2 * v) + (links + v + v + 2 * x + 2 * v)
     return (links + 2 * v) + (links + 2 * v + 2 * x + 2 * v) + 3 * v
@@ -824,10 +826,13 @@ def main():
                     torch, lambda: sp.cg_solve(Gl, mass, b, tol=tol, inner=prec, workspace=ws), max(1, args.steps))
                 tl, tl_se = mean_stderr(pl)
                 el = float(torch.linalg.norm(xl - xref) / torch.linalg.norm(xref))
+                ib = iteration_bytes_per_site(prec, rc)
                 low[f"{prec}_r{rc}"] = {"s": tl, "s_stderr": tl_se, "solves": len(pl), "iters": stl.iters,
                                         "reliable_updates": stl.reliable_updates,
                                         "true_rel_resid": stl.true_rel_resid, "err_vs_fp64_1e12": el,
-                                        "err_vs_oracle_samples": golden_err(xl, dims, mass)}
+                                        "err_vs_oracle_samples": golden_err(xl, dims, mass),
+                                        "speedup_vs_inner": t_mixed / tl, "iteration_bytes_per_site": ib,
+                                        "iteration_hbm_frac": ib * lat.Vh * stl.iters / tl / 1e9 / HBM_PEAK_GBS}
                 log(f"{prec} r{rc}: {tl * 1e3:.2f} ms/solve iters={stl.iters} err={el:.2e}")
                 del Gl
         extra["storage_16bit"] = low
