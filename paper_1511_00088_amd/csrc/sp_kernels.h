@@ -131,14 +131,15 @@ __device__ __forceinline__ Rhs<N> rhs_of(const D& d, const GroupDev& G, int gate
 }
 
 // This thread's share of the second reduction stage over n block partials of NV arrays: acc[q] += a[q][b] for
-// b = threadIdx.x, + blockDim.x, ... < n, added in increasing b (the order that makes every block of a launch
+// b = b_first, + blockDim.x, ... < n, added in increasing b (the order that makes every block of a launch
 // reach the same total, bit for bit). The loads go out eight at a time: a plain loop of dependent adds waits
 // for each load in turn, one memory round trip per partial.
 template <int NV>
-__device__ __forceinline__ void strided_sums(double (&acc)[NV], const double* const (&a)[NV], int n) {
+__device__ __forceinline__ void strided_sums_from(double (&acc)[NV], const double* const (&a)[NV], int n,
+                                                  int b_first) {
     constexpr int K = 8;
     const int nt = blockDim.x;
-    for (int b0 = threadIdx.x; b0 < n; b0 += K * nt) {
+    for (int b0 = b_first; b0 < n; b0 += K * nt) {
         double v[K][NV];
 #pragma unroll
         for (int j = 0; j < K; ++j)
@@ -150,6 +151,34 @@ __device__ __forceinline__ void strided_sums(double (&acc)[NV], const double* co
             for (int q = 0; q < NV; ++q)
                 if (b0 + j * nt < n) acc[q] += v[j][q];
     }
+}
+
+// The same sums split around the caller's own loads: strided_head loads this thread's first HEAD partials
+// (b = threadIdx.x + j blockDim.x, j < HEAD) with no branch (indices clamped to n - 1) and leaves them unused,
+// so that the loads the caller issues next do not wait for them; strided_tail adds those below n, then any
+// further partials, in the same increasing order as strided_sums_from.
+constexpr int HEAD = 4;
+template <int NV>
+__device__ __forceinline__ void strided_head(double (&v)[HEAD][NV], const double* const (&a)[NV], int n) {
+    const int nt = blockDim.x;
+#pragma unroll
+    for (int j = 0; j < HEAD; ++j) {
+        const int b = threadIdx.x + j * nt;
+        const int c = b < n ? b : n - 1;
+#pragma unroll
+        for (int q = 0; q < NV; ++q) v[j][q] = a[q][c];
+    }
+}
+template <int NV>
+__device__ __forceinline__ void strided_tail(double (&acc)[NV], const double (&v)[HEAD][NV],
+                                             const double* const (&a)[NV], int n) {
+#pragma unroll
+    for (int j = 0; j < HEAD; ++j)
+        if (threadIdx.x + j * blockDim.x < n) {
+#pragma unroll
+            for (int q = 0; q < NV; ++q) acc[q] += v[j][q];
+        }
+    strided_sums_from<NV>(acc, a, n, threadIdx.x + HEAD * blockDim.x);
 }
 
 // First reduction stage: block totals of NV values per thread, stored by thread 0 as dst[gblk][NV].
@@ -170,9 +199,9 @@ __device__ __forceinline__ void block_partials(double* dst, int gblk, double (&v
 //   DS_UPDATE: q = m^2 p - D_eo t (not stored); x += alpha p; r -= alpha q; block partials of |r|^2
 //   DS_UPDATE_FUSED (one system): as DS_UPDATE, but every block forms alpha itself from the partials of
 //              |D_oe p|^2 and |p|^2 (summed in the same order in every block, so all blocks agree bit for
-//              bit); the loads are issued before the gather and used after it. Saves the alpha finalize
-//              launch when the partials are few; |r|^2 partials go to partials_r, Re<p,Ap> and alpha to
-//              rec for k_xpay_fused, which takes the place of the update finalize.
+//              bit); the first partials are loaded before the gathers and summed after them. Saves the
+//              alpha finalize launch when the partials are few; |r|^2 partials go to partials_r, Re<p,Ap>
+//              and alpha to rec for k_xpay_fused, which takes the place of the update finalize.
 // ------------------------------------------------------------------------------------------------------
 enum DsMode : int { DS_PLAIN = 0, DS_NORM = 1, DS_UPDATE = 2, DS_UPDATE_FUSED = 3 };
 
@@ -208,10 +237,9 @@ __global__ __launch_bounds__(256) void k_dslash(D d, int p, int in_slot, int out
     constexpr bool FUSED = MODE == DS_UPDATE_FUSED;
     static_assert(!FUSED || N == 1, "alpha is formed in-block for one system only");
     double pre[2] = {0.0, 0.0};  // FUSED: this thread's share of the |D_oe p|^2 and |p|^2 partials
-    if constexpr (FUSED) {
-        const double* const src[2] = {G.partials, G.partials_p};
-        strided_sums<2>(pre, src, G.nblk);
-    }
+    double head[HEAD][2];
+    const double* const psrc[2] = {G.partials, G.partials_p};
+    if constexpr (FUSED) strided_head<2>(head, psrc, G.nblk);
     const bool live = cb < g.Vh;
     Vec3<R> acc[N];
 #pragma unroll
@@ -257,6 +285,7 @@ __global__ __launch_bounds__(256) void k_dslash(D d, int p, int in_slot, int out
     R alpha_blk = R(0);
     if constexpr (FUSED) {
         __shared__ double a_sh;
+        strided_tail<2>(pre, head, psrc, G.nblk);
         block_sum<2>(pre);
         if (threadIdx.x == 0) {
             const SolverState* st = h.st[0];
@@ -493,13 +522,15 @@ __global__ __launch_bounds__(256) void k_xpay_fused(DescSingle d, SolverState* _
     const bool live = cb < Vh;
     // loads that do not depend on the state go first
     double part[1] = {0.0};
+    double head[HEAD][1];
     const double* const src[1] = {G.partials_r};
-    strided_sums<1>(part, src, G.nblk);
+    strided_head<1>(head, src, G.nblk);
     Vec3<R> rv = vzero<R>(), pv = vzero<R>();
     if (live) {
         rv = VF::load(d.sys.v[S_R], Vh, cb);
         pv = VF::load(d.sys.v[S_P], Vh, cb);
     }
+    strided_tail<1>(part, head, src, G.nblk);
     block_sum<1>(part);
     __shared__ double beta_sh;
     __shared__ int go_sh, ru_sh;
@@ -579,10 +610,9 @@ __global__ __launch_bounds__(256) void k_norm_rec(DescSingle d, SolverState* __r
     }
     const bool direct = (flags & ST_T_STALE) != 0;
     double part[1] = {0.0};
-    if (!direct) {
-        const double* const src[1] = {G.partials_r};
-        strided_sums<1>(part, src, G.nblk);
-    }
+    double head[HEAD][1];
+    const double* const psrc[1] = {G.partials_r};
+    if (!direct) strided_head<1>(head, psrc, G.nblk);
     Vec3<R> acc = vzero<R>(), told = vzero<R>(), rv = vzero<R>(), pv = vzero<R>();
     if (live) {
         acc = dslash_site<LP, RECON, VP, NT>(g, G.links_lo, direct ? S.v[S_P] : S.v[S_R], 1, site_of(g, 1, cb));
@@ -594,7 +624,10 @@ __global__ __launch_bounds__(256) void k_norm_rec(DescSingle d, SolverState* __r
     }
     __shared__ double beta_sh;
     __shared__ int go_sh;
-    if (!direct) block_sum<1>(part);
+    if (!direct) {
+        strided_tail<1>(part, head, psrc, G.nblk);
+        block_sum<1>(part);
+    }
     if (threadIdx.x == 0) {
         SolverState s = *st;
         bool go = true;

@@ -1,5 +1,5 @@
 // Streaming-bandwidth probe: the attainable HBM rate that the bandwidth-bound kernels of this library are
-// judged against (the paper, Sec. 4 and Table 3, argues CG performance from memory bandwidth per flop).
+// measured against (the paper, Sec. 4 and Table 3, argues CG performance from memory bandwidth per flop).
 // Three kernels over n 16-byte words, each lane moving whole 16-byte words, K words per lane in flight:
 //   read  : s += a[i]        (one 16-byte word read per element; a per-block sum is written so that the loads
 //                             are not removed)
