@@ -632,6 +632,10 @@ struct alignas(64) SolverState {
 };
 
 static constexpr int STALL_LIMIT = 6;
+// A kept direction assumes that the recursive residual tracked the true one. When the true |r|^2 at a reliable
+// update exceeds the recursive one by more than this factor, the inner operator's error has come to dominate the
+// residual (fixed-point links with updates too far apart), and the update restarts the direction instead.
+static constexpr double DRIFT_RESTART = 1.5;
 
 __device__ __forceinline__ void fin_alpha(SolverState* st, double pq) {
     st->pq = pq;
@@ -677,7 +681,8 @@ __device__ __forceinline__ void fin_update(SolverState* st, double rho_new, bool
 // update becomes
 //   p = r + beta (p - c r), beta = rho_true / rho, c = Re<r,p> / rho_true
 // which restores the orthogonality of the old direction to the new residual, or p = r (restart) when the
-// iterated vectors are stored in 16 bits.
+// iterated vectors are stored in 16 bits or the true residual has drifted from the recursive one
+// (DRIFT_RESTART).
 __device__ __forceinline__ void fin_resid(SolverState* st, double rho_true, double rp, int init) {
     st->true_rho = rho_true;
     if (!init) st->ru_count += 1;
@@ -707,7 +712,7 @@ __device__ __forceinline__ void fin_resid(SolverState* st, double rho_true, doub
         st->beta = 0.0;  // p = r
         st->xpay_a = 1.0;
     } else {
-        if (st->restart) {
+        if (st->restart || rho_true > DRIFT_RESTART * st->rho_new) {
             st->beta = 0.0;
             st->xpay_a = 1.0;
         } else {
