@@ -916,7 +916,9 @@ def main():
                                f"SU(3) links eps=0.3, m={mass}, Gaussian source, tol={tol}",
                    "dims": list(dims), "mass": mass, "tol": tol, "inner": args.inner, "recon": args.recon,
                    "links": args.links or args.inner,
-                   "reliable_update": "FP64 true residual every 100 iterations or on |r| < 0.1 |r_ru|",
+                   "reliable_update": ("FP64 true residual every 75 iterations or on |r| < 0.1 |r_ru|"
+                                       if args.links == "i16" else
+                                       "FP64 true residual every 100 iterations or on |r| < 0.1 |r_ru|"),
                    "parallelism": "single GPU"},
         "iters": st.iters,
         "reliable_updates": st.reliable_updates,

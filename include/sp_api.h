@@ -93,18 +93,19 @@ typedef struct {
  *  delta      reliable update when |r_iterated| < delta * |r at the last update| (0 disables; ignored
  *             for SP_F64; checked at the end of each poll chunk)
  *  ru_every   reliable update at least every ru_every iterations (ignored for SP_F64; <= 0 picks 100, or
- *             50 for FP32 iterations on SP_I16 links; checked at the end of each poll chunk)
+ *             for FP32 iterations on SP_I16 links 75 with 75-iteration chunks and 50 otherwise; checked at
+ *             the end of each poll chunk)
  *  poll_chunk iterations per device-side chunk (one hipGraph launch) between host convergence polls
- *             (<= 0 picks 100 for a single solve with FP32 iterations on FP32 links, or SP_F64, of at least
- *             2^16 even sites; 25 otherwise)
+ *             (<= 0 picks, for a single solve of at least 2^16 even sites, 100 with FP32 iterations on FP32
+ *             links or SP_F64 and 75 with FP32 iterations on SP_I16 links; 25 otherwise)
  *  use_x0     1: x_e holds the initial guess on entry; 0: start from zero
  *  use_graph  1: capture each chunk in a hipGraph and replay it; 0: launch kernels one by one
  * A reliable update also runs whenever the iterated residual reaches tol, at the iteration cap, and (for
  * SP_F32, SP_F16, SP_BF16) when the iterated residual falls three decades below the true residual of the
- * last update. After
- * it, FP32 iterations on FP32 or SP_I16 links keep the search direction (re-orthogonalised against the new
- * residual); FP16 or BF16 storage of the vectors or of the links restarts it from the residual (a kept
- * direction stalls when the rounded links move the operator by much more than its smallest eigenvalue). */
+ * last update. After it, FP32 iterations on FP32 or SP_I16 links keep the search direction
+ * (re-orthogonalised against the new residual) unless the true |r|^2 exceeds the iterated one by more than
+ * 1.5x; FP16 or BF16 storage of the vectors or of the links restarts it from the residual (a kept direction
+ * stalls when the rounded links move the operator by much more than its smallest eigenvalue). */
 typedef struct {
     double tol;
     int32_t max_iter;

@@ -558,7 +558,7 @@ void release_graphs() {
 // ---------------------------------------------------------------------------------------------------
 // Solve driver shared by sp_cg_solve (DescSingle) and sp_cg_solve_batched (DescBatch)
 // ---------------------------------------------------------------------------------------------------
-SolverState initial_state(const sp_system& s, const sp_cg_params* prm) {
+SolverState initial_state(const sp_system& s, const sp_cg_params* prm, int chunk) {
     SolverState st;
     memset(&st, 0, sizeof st);
     st.tol2 = prm->tol * prm->tol;
@@ -567,16 +567,17 @@ SolverState initial_state(const sp_system& s, const sp_cg_params* prm) {
     st.floor2 = prm->inner != SP_F64 ? 1e-6 : 0.0;  // |r| three decades below the last true residual
     st.m2 = s.mass * s.mass;
     st.max_iter = prm->max_iter;
-    // FP32 iterations on 16-bit fixed-point links keep the direction and update every 50 iterations (their
-    // links are within 2^-16 of the true ones); FP16 and BF16 storage, of the vectors or of the links, moves
-    // the inner operator by about 2^-11 |A| or more, far more than the smallest eigenvalue m^2 of a light-quark
-    // system, and a direction kept across an update then stalls the solve: they restart it (p = r) at every
-    // reliable update
+    // FP32 iterations on 16-bit fixed-point links keep the direction and update every 50 iterations, or at every
+    // end of the 75-iteration chunks of large single solves (their links are within 2^-16 of the true ones; the
+    // update restarts the direction if the residual has drifted regardless); FP16 and BF16 storage, of the
+    // vectors or of the links, moves the inner operator by about 2^-11 |A| or more, far more than the smallest
+    // eigenvalue m^2 of a light-quark system, and a direction kept across an update then stalls the solve: they
+    // restart it (p = r) at every reliable update
     const bool fixed16_links = prm->inner == SP_F32 && s.U && s.U->lo_prec == SP_I16;
     const bool float16_links = prm->inner == SP_F32 && s.U && (s.U->lo_prec == SP_F16 || s.U->lo_prec == SP_BF16);
     int every = prm->ru_every;
     if (prm->inner == SP_F64) every = INT_MAX;
-    else if (every <= 0) every = fixed16_links ? 50 : 100;
+    else if (every <= 0) every = fixed16_links ? (chunk == 75 ? 75 : 50) : 100;
     st.ru_every = every;
     st.restart = (prm->inner == SP_F16 || prm->inner == SP_BF16 || float16_links) ? 1 : 0;
     return st;
@@ -619,12 +620,28 @@ int solve_impl(int nsys, const sp_system* systems, const sp_cg_params* prm, sp_c
         if ((L.inner != SP_F64) && (G.U->recon != L.groups[0].U->recon || G.U->lo_prec != L.groups[0].U->lo_prec))
             return fail(SP_ERR_UNSUPPORTED, "all systems of a batch must share the link packing");
 
+    // Iterations per chunk, when the caller leaves it, for single solves of at least 2^16 even sites, where each
+    // chunk boundary costs a graph launch and a state poll (about 17 us): 100 with FP32 iterations on FP32 links
+    // (or plain FP64 CG), where the t recurrence and the kept direction need no earlier reset (20^3x64: 499
+    // iterations at any length from 20 to 100, 23.7 -> 23.4 ms); 75 on fixed-point links, with a reliable update
+    // at every chunk end (20^3x64: 511-514 iterations and 8 updates, 18.0 ms, against 502 and 11, 18.1 ms, with
+    // chunks of 25 and an update every 50). 25 otherwise: with FP16 or BF16 links or vectors the reliable-update
+    // triggers, checked at chunk ends, set the iteration count, and small or batched solves keep the finer polling.
+    const int lo0 = L.inner == SP_F64 ? SP_F64 : L.groups[0].U->lo_prec;
+    int chunk = prm->poll_chunk;
+    if (chunk <= 0) {
+        const bool full_links = L.inner == SP_F64 || (L.inner == SP_F32 && lo0 == SP_F32);
+        const bool fixed_links = L.inner == SP_F32 && lo0 == SP_I16;
+        const bool large = !batched && L.groups[0].g.Vh >= (1 << 16);
+        chunk = large && full_links ? 100 : large && fixed_links ? 75 : 25;
+    }
+
     // ---- control block on the host ----
     HIP_TRY(g_upload.ensure(L.ctrl_bytes));
     char* h = (char*)g_upload.p;
     memset(h, 0, L.ctrl_bytes);
     SolverState* hst = (SolverState*)(h + L.states_off);
-    for (int i = 0; i < nsys; ++i) hst[i] = initial_state(systems[i], prm);
+    for (int i = 0; i < nsys; ++i) hst[i] = initial_state(systems[i], prm, chunk);
     GroupDev* hg = (GroupDev*)(h + L.gdesc_off);
     SysDev* hs = (SysDev*)(h + L.sdesc_off);
     int sys_counter = 0;
@@ -678,17 +695,6 @@ int solve_impl(int nsys, const sp_system* systems, const sp_cg_params* prm, sp_c
     pl.ngroups = (int)L.groups.size();
     pl.cfg = L.cfg;
 
-    // Iterations per chunk, when the caller leaves it: 100 for a single solve with FP32 iterations on FP32 links
-    // (or plain FP64 CG) of at least 2^16 even sites, where each chunk boundary costs a graph launch and a state
-    // poll (about 17 us) and the t recurrence and the kept direction need no earlier reset (20^3x64: 499
-    // iterations at any length from 20 to 100, 23.7 -> 23.4 ms); 25 otherwise: with 16-bit links or vectors the
-    // reliable-update triggers, checked at chunk ends, set the iteration count (fixed-point links: 502 iterations
-    // with 25, 523-760 with 32-64), and small or batched solves keep the finer polling.
-    int chunk = prm->poll_chunk;
-    if (chunk <= 0) {
-        const bool full_links = pl.inner == SP_F64 || (pl.inner == SP_F32 && pl.lp == SP_F32);
-        chunk = (!batched && full_links && L.groups[0].g.Vh >= (1 << 16)) ? 100 : 25;
-    }
     HIP_TRY(g_poll.ensure(2 * sizeof(SolverState) * nsys));
     SolverState* slots[2] = {(SolverState*)g_poll.p, (SolverState*)g_poll.p + nsys};
 

@@ -123,10 +123,10 @@ def test_solve_workload_vs_oracle_samples(lp, recon):
 
 def test_fixed_point_links_robust_to_the_update_schedule():
     """Fixed-point links keep the direction across reliable updates, which pays while the updates come often
-    enough for the recursive residual to track the true one (every 50 iterations: as many iterations as FP32
-    links). With updates 150 iterations apart the drift dominates, and a kept direction took 1,238 iterations
-    on this system; the update then restarts the direction, which bounds the count near that of the restarted
-    FP16-link solve (about 1.2 times FP32's)."""
+    enough for the recursive residual to track the true one (the default, an update at every 75-iteration chunk
+    end: 511 iterations against FP32 links' 499). With updates 150 iterations apart the drift dominates, and a
+    kept direction took 1,238 iterations on this system; the update then restarts the direction, which bounds
+    the count near that of the restarted FP16-link solve (about 1.2 times FP32's)."""
     c = _cfg1()
     dims, U, m, b = c["dims"], c["links"], c["mass"], c["source"]
     sp.tune_load(tune_file())
@@ -134,7 +134,7 @@ def test_fixed_point_links_robust_to_the_update_schedule():
     G = gauge16(dims, U, "i16", 12)
     _, s32 = sp.cg_solve(G32, m, to_dev(b), tol=1e-8, inner="f32")
     cbs, ref = cfg1_golden()
-    for every, cap in ((0, 1.03), (150, 1.3)):
+    for every, cap in ((0, 1.05), (150, 1.3)):
         announce(f"links16 i16 r12 20^3x64 update every {every or 'default'}")
         x, st = sp.cg_solve(G, m, to_dev(b), tol=1e-8, inner="f32", ru_every=every)
         x = to_host(x)
