@@ -94,7 +94,8 @@ typedef struct {
  *             for SP_F64; checked at the end of each poll chunk)
  *  ru_every   reliable update at least every ru_every iterations (ignored for SP_F64; <= 0 picks 100, or
  *             for FP32 iterations on SP_I16 links 75 with 75-iteration chunks and 50 otherwise; checked at
- *             the end of each poll chunk)
+ *             the end of each poll chunk). With BF16 storage every update restarts the search direction, so
+ *             short intervals slow the solve (every 50 iterations: 1,649 against 733 at 20^3x64, m = 0.01)
  *  poll_chunk iterations per device-side chunk (one hipGraph launch) between host convergence polls
  *             (<= 0 picks, for a single solve of at least 2^16 even sites, 100 with FP32 iterations on FP32
  *             links or SP_F64 and 75 with FP32 iterations on SP_I16 links; 25 otherwise)
@@ -102,10 +103,10 @@ typedef struct {
  *  use_graph  1: capture each chunk in a hipGraph and replay it; 0: launch kernels one by one
  * A reliable update also runs whenever the iterated residual reaches tol, at the iteration cap, and (for
  * SP_F32, SP_F16, SP_BF16) when the iterated residual falls three decades below the true residual of the
- * last update. After it, FP32 iterations on FP32 or SP_I16 links keep the search direction
- * (re-orthogonalised against the new residual) unless the true |r|^2 exceeds the iterated one by more than
- * 1.5x; FP16 or BF16 storage of the vectors or of the links restarts it from the residual (a kept direction
- * stalls when the rounded links move the operator by much more than its smallest eigenvalue). */
+ * last update. After it the search direction is kept (re-orthogonalised against the new residual) unless
+ * the true |r|^2 exceeds the iterated one by more than 1.5x (FP32 iterations on FP32 or SP_I16 links) or
+ * 1.25x (FP16 storage of the vectors or of the links), when it restarts from the residual; BF16 storage
+ * restarts it at every update. */
 typedef struct {
     double tol;
     int32_t max_iter;

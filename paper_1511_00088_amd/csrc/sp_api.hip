@@ -567,19 +567,21 @@ SolverState initial_state(const sp_system& s, const sp_cg_params* prm, int chunk
     st.floor2 = prm->inner != SP_F64 ? 1e-6 : 0.0;  // |r| three decades below the last true residual
     st.m2 = s.mass * s.mass;
     st.max_iter = prm->max_iter;
-    // FP32 iterations on 16-bit fixed-point links keep the direction and update every 50 iterations, or at every
-    // end of the 75-iteration chunks of large single solves (their links are within 2^-16 of the true ones; the
-    // update restarts the direction if the residual has drifted regardless); FP16 and BF16 storage, of the
-    // vectors or of the links, moves the inner operator by about 2^-11 |A| or more, far more than the smallest
-    // eigenvalue m^2 of a light-quark system, and a direction kept across an update then stalls the solve: they
-    // restart it (p = r) at every reliable update
+    // FP32 iterations on FP32 or 16-bit fixed-point links keep the direction across a reliable update unless
+    // the true |r|^2 exceeds the recursive one by more than 1.5x; the fixed-point links (within 2^-16 of the
+    // true ones) update every 50 iterations, or at every end of the 75-iteration chunks of large single solves.
+    // FP16 and BF16 storage, of the vectors or of the links, moves the inner operator by about 2^-11 |A| and
+    // 2^-8 |A|, far more than the smallest eigenvalue m^2 of a light-quark system: FP16 keeps the direction
+    // unless the residual has drifted by 1.25x (a kept direction without that check stalls the solve), BF16
+    // restarts it at every update (fewer iterations at the default schedule than any drift factor measured)
     const bool fixed16_links = prm->inner == SP_F32 && s.U && s.U->lo_prec == SP_I16;
-    const bool float16_links = prm->inner == SP_F32 && s.U && (s.U->lo_prec == SP_F16 || s.U->lo_prec == SP_BF16);
+    const bool f16 = prm->inner == SP_F16 || (prm->inner == SP_F32 && s.U && s.U->lo_prec == SP_F16);
+    const bool bf16 = prm->inner == SP_BF16 || (prm->inner == SP_F32 && s.U && s.U->lo_prec == SP_BF16);
     int every = prm->ru_every;
     if (prm->inner == SP_F64) every = INT_MAX;
     else if (every <= 0) every = fixed16_links ? (chunk == 75 ? 75 : 50) : 100;
     st.ru_every = every;
-    st.restart = (prm->inner == SP_F16 || prm->inner == SP_BF16 || float16_links) ? 1 : 0;
+    st.drift = bf16 ? 0.0 : f16 ? 1.25 : 1.5;
     return st;
 }
 

@@ -627,15 +627,13 @@ struct alignas(64) SolverState {
     double true_rho;  // last true |r|^2
     double best_rho;  // best true |r|^2 so far (stagnation)
     double m2;        // mass^2
+    double drift;     // a reliable update restarts the direction (p = r) when the true |r|^2 exceeds the
+                      // recursive one by more than this factor (0: at every update)
     int iter, iter_last_ru, ru_count, flags;
-    int stall, max_iter, ru_every, restart;  // restart: p = r after a reliable update (16-bit storage)
+    int stall, max_iter, ru_every;
 };
 
 static constexpr int STALL_LIMIT = 6;
-// A kept direction assumes that the recursive residual tracked the true one. When the true |r|^2 at a reliable
-// update exceeds the recursive one by more than this factor, the inner operator's error has come to dominate the
-// residual (fixed-point links with updates too far apart), and the update restarts the direction instead.
-static constexpr double DRIFT_RESTART = 1.5;
 
 __device__ __forceinline__ void fin_alpha(SolverState* st, double pq) {
     st->pq = pq;
@@ -681,8 +679,9 @@ __device__ __forceinline__ void fin_update(SolverState* st, double rho_new, bool
 // update becomes
 //   p = r + beta (p - c r), beta = rho_true / rho, c = Re<r,p> / rho_true
 // which restores the orthogonality of the old direction to the new residual, or p = r (restart) when the
-// iterated vectors are stored in 16 bits or the true residual has drifted from the recursive one
-// (DRIFT_RESTART).
+// true residual has drifted from the recursive one by more than the factor st->drift: a kept direction assumes
+// that the recursion tracked the true residual, and once the inner operator's error dominates the residual it
+// no longer does.
 __device__ __forceinline__ void fin_resid(SolverState* st, double rho_true, double rp, int init) {
     st->true_rho = rho_true;
     if (!init) st->ru_count += 1;
@@ -712,7 +711,7 @@ __device__ __forceinline__ void fin_resid(SolverState* st, double rho_true, doub
         st->beta = 0.0;  // p = r
         st->xpay_a = 1.0;
     } else {
-        if (st->restart || rho_true > DRIFT_RESTART * st->rho_new) {
+        if (rho_true > st->drift * st->rho_new) {
             st->beta = 0.0;
             st->xpay_a = 1.0;
         } else {
