@@ -490,6 +490,7 @@ hipError_t enqueue_chunk(const D& d, const Plan& pl, int iters, hipStream_t s) {
 // hipGraph cache: one executable graph per (descriptor bytes, plan, chunk length)
 // ---------------------------------------------------------------------------------------------------
 std::map<std::string, hipGraphExec_t> g_graphs;
+constexpr size_t kMaxGraphs = 64;
 hipStream_t g_capture_stream = nullptr;
 int g_capture_device = -1;
 
@@ -540,7 +541,6 @@ hipError_t chunk_graph(const D& d, const Plan& pl, int iters, const SolverState*
         return ee;
     }
     if (e) return e;
-    if (g_graphs.size() >= 64) release_graphs();
     hipGraphExec_t exec = nullptr;
     e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
@@ -718,23 +718,31 @@ int solve_impl(int nsys, const sp_system* systems, const sp_cg_params* prm, sp_c
     };
     HIP_TRY(setup());
 
-    // with graphs, one per poll slot: each ends by copying the states into its slot
+    // with graphs, one per poll slot: each ends by copying the states into its slot. Near convergence the
+    // chunks are shorter (tail iterations), so that the last one does not run many iterations past the point
+    // where every system stopped: those return at once, but each still costs a launch.
+    const int tail = std::min(chunk, 25);
     const SolverState* dev_states = (const SolverState*)(base + L.states_off);
-    hipGraphExec_t exec[2] = {nullptr, nullptr};
-    if (prm->use_graph) {
+    hipGraphExec_t exec[2] = {nullptr, nullptr}, exec_tail[2] = {nullptr, nullptr};
+    auto graphs = [&](int len, hipGraphExec_t* out) -> hipError_t {
         for (int k = 0; k < 2; ++k) {
-            hipError_t e = batched ? chunk_graph(db, pl, chunk, dev_states, slots[k], nsys, &exec[k])
-                                   : chunk_graph(ds, pl, chunk, dev_states, slots[k], nsys, &exec[k]);
-            HIP_TRY(e);
+            hipError_t e = batched ? chunk_graph(db, pl, len, dev_states, slots[k], nsys, &out[k])
+                                   : chunk_graph(ds, pl, len, dev_states, slots[k], nsys, &out[k]);
+            if (e) return e;
         }
-    }
+        return hipSuccess;
+    };
+    // the cache is trimmed before this solve takes any graph from it (its two chunk lengths add at most four),
+    // never while one it holds may be queued
+    if (prm->use_graph && g_graphs.size() + 4 > kMaxGraphs) release_graphs();
+    if (prm->use_graph) HIP_TRY(graphs(chunk, exec));
     Events ev;
     HIP_TRY(ev.create());
     // Chunks are pipelined: chunk c is queued before the state written by chunk c-1 is inspected, so the
     // GPU does not wait for the host. Near convergence (estimated from the residual decay between polls)
     // the host waits for each chunk before queueing the next one, so that no chunk is launched only to
-    // find every system stopped.
-    const long max_chunks = (long)prm->max_iter / chunk + 64;
+    // find every system stopped, and the chunks take `tail` iterations.
+    const long max_chunks = (long)prm->max_iter / tail + 64;
     SolverState* poll = nullptr;
     std::vector<double> last_rho(nsys, -1.0);
     std::vector<int> last_iter(nsys, 0);
@@ -756,10 +764,13 @@ int solve_impl(int nsys, const sp_system* systems, const sp_cg_params* prm, sp_c
             char cr[48];
             snprintf(cr, sizeof cr, "chunk %ld", c);
             const TraceRange chunk_range(cr);
-            if (exec[c & 1]) {
-                HIP_TRY(hipGraphLaunch(exec[c & 1], stream));
+            const int len = careful ? tail : chunk;
+            if (prm->use_graph && len != chunk && !exec_tail[0]) HIP_TRY(graphs(len, exec_tail));
+            hipGraphExec_t g = len != chunk ? exec_tail[c & 1] : exec[c & 1];
+            if (g) {
+                HIP_TRY(hipGraphLaunch(g, stream));
             } else {
-                HIP_TRY(batched ? enqueue_chunk(db, pl, chunk, stream) : enqueue_chunk(ds, pl, chunk, stream));
+                HIP_TRY(batched ? enqueue_chunk(db, pl, len, stream) : enqueue_chunk(ds, pl, len, stream));
                 HIP_TRY(hipMemcpyAsync(slots[c & 1], dev_states, sizeof(SolverState) * nsys, hipMemcpyDeviceToHost,
                                        stream));
             }

@@ -153,32 +153,43 @@ __device__ __forceinline__ void strided_sums_from(double (&acc)[NV], const doubl
     }
 }
 
-// The same sums split around the caller's own loads: strided_head loads this thread's first HEAD partials
-// (b = threadIdx.x + j blockDim.x, j < HEAD) with no branch (indices clamped to n - 1) and leaves them unused,
-// so that the loads the caller issues next do not wait for them; strided_tail adds those below n, then any
-// further partials, in the same increasing order as strided_sums_from.
+// The same sums split around the caller's own loads, when every thread has at most HEAD partials (up to
+// HEAD x blockDim.x blocks): strided_head loads them with no branch (indices clamped to n - 1) and leaves them
+// unused, so that the loads the caller issues next do not wait for them, and strided_tail adds those below n
+// in the same increasing order. With more partials strided_head sums them all at once, eight loads in flight
+// (moving them after the operator's gathers put two or more dependent rounds of loads after it: 2% slower
+// iterations on 32^3x64), and strided_tail adds nothing.
 constexpr int HEAD = 4;
 template <int NV>
-__device__ __forceinline__ void strided_head(double (&v)[HEAD][NV], const double* const (&a)[NV], int n) {
+__device__ __forceinline__ void strided_head(double (&acc)[NV], double (&v)[HEAD][NV], const double* const (&a)[NV],
+                                             int n) {
     const int nt = blockDim.x;
+    if (n <= HEAD * nt) {
 #pragma unroll
-    for (int j = 0; j < HEAD; ++j) {
-        const int b = threadIdx.x + j * nt;
-        const int c = b < n ? b : n - 1;
+        for (int j = 0; j < HEAD; ++j) {
+            const int b = threadIdx.x + j * nt;
+            const int c = b < n ? b : n - 1;
 #pragma unroll
-        for (int q = 0; q < NV; ++q) v[j][q] = a[q][c];
+            for (int q = 0; q < NV; ++q) v[j][q] = a[q][c];
+        }
+    } else {
+        strided_sums_from<NV>(acc, a, n, threadIdx.x);
+#pragma unroll
+        for (int j = 0; j < HEAD; ++j)
+#pragma unroll
+            for (int q = 0; q < NV; ++q) v[j][q] = 0.0;
     }
 }
 template <int NV>
-__device__ __forceinline__ void strided_tail(double (&acc)[NV], const double (&v)[HEAD][NV],
-                                             const double* const (&a)[NV], int n) {
+__device__ __forceinline__ void strided_tail(double (&acc)[NV], const double (&v)[HEAD][NV], int n) {
+    if (n <= HEAD * (int)blockDim.x) {
 #pragma unroll
-    for (int j = 0; j < HEAD; ++j)
-        if (threadIdx.x + j * blockDim.x < n) {
+        for (int j = 0; j < HEAD; ++j)
+            if (threadIdx.x + j * blockDim.x < n) {
 #pragma unroll
-            for (int q = 0; q < NV; ++q) acc[q] += v[j][q];
-        }
-    strided_sums_from<NV>(acc, a, n, threadIdx.x + HEAD * blockDim.x);
+                for (int q = 0; q < NV; ++q) acc[q] += v[j][q];
+            }
+    }
 }
 
 // First reduction stage: block totals of NV values per thread, stored by thread 0 as dst[gblk][NV].
@@ -239,7 +250,7 @@ __global__ __launch_bounds__(256) void k_dslash(D d, int p, int in_slot, int out
     double pre[2] = {0.0, 0.0};  // FUSED: this thread's share of the |D_oe p|^2 and |p|^2 partials
     double head[HEAD][2];
     const double* const psrc[2] = {G.partials, G.partials_p};
-    if constexpr (FUSED) strided_head<2>(head, psrc, G.nblk);
+    if constexpr (FUSED) strided_head<2>(pre, head, psrc, G.nblk);
     const bool live = cb < g.Vh;
     Vec3<R> acc[N];
 #pragma unroll
@@ -285,7 +296,7 @@ __global__ __launch_bounds__(256) void k_dslash(D d, int p, int in_slot, int out
     R alpha_blk = R(0);
     if constexpr (FUSED) {
         __shared__ double a_sh;
-        strided_tail<2>(pre, head, psrc, G.nblk);
+        strided_tail<2>(pre, head, G.nblk);
         block_sum<2>(pre);
         if (threadIdx.x == 0) {
             const SolverState* st = h.st[0];
@@ -524,13 +535,13 @@ __global__ __launch_bounds__(256) void k_xpay_fused(DescSingle d, SolverState* _
     double part[1] = {0.0};
     double head[HEAD][1];
     const double* const src[1] = {G.partials_r};
-    strided_head<1>(head, src, G.nblk);
+    strided_head<1>(part, head, src, G.nblk);
     Vec3<R> rv = vzero<R>(), pv = vzero<R>();
     if (live) {
         rv = VF::load(d.sys.v[S_R], Vh, cb);
         pv = VF::load(d.sys.v[S_P], Vh, cb);
     }
-    strided_tail<1>(part, head, src, G.nblk);
+    strided_tail<1>(part, head, G.nblk);
     block_sum<1>(part);
     __shared__ double beta_sh;
     __shared__ int go_sh, ru_sh;
@@ -612,7 +623,7 @@ __global__ __launch_bounds__(256) void k_norm_rec(DescSingle d, SolverState* __r
     double part[1] = {0.0};
     double head[HEAD][1];
     const double* const psrc[1] = {G.partials_r};
-    if (!direct) strided_head<1>(head, psrc, G.nblk);
+    if (!direct) strided_head<1>(part, head, psrc, G.nblk);
     Vec3<R> acc = vzero<R>(), told = vzero<R>(), rv = vzero<R>(), pv = vzero<R>();
     if (live) {
         acc = dslash_site<LP, RECON, VP, NT>(g, G.links_lo, direct ? S.v[S_P] : S.v[S_R], 1, site_of(g, 1, cb));
@@ -625,7 +636,7 @@ __global__ __launch_bounds__(256) void k_norm_rec(DescSingle d, SolverState* __r
     __shared__ double beta_sh;
     __shared__ int go_sh;
     if (!direct) {
-        strided_tail<1>(part, head, psrc, G.nblk);
+        strided_tail<1>(part, head, G.nblk);
         block_sum<1>(part);
     }
     if (threadIdx.x == 0) {

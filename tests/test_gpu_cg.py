@@ -75,6 +75,40 @@ def test_graph_and_eager_bitwise_equal():
     assert torch.equal(x1, x2) and torch.equal(x1, x3)
 
 
+def test_tail_chunks_graph_and_eager_bitwise_equal():
+    """A single solve of 2^16 even sites takes 100-iteration chunks, and 25-iteration ones once the host
+    expects convergence within the chunk in flight and the next: graph replay and eager launches take the same
+    chunk lengths and agree bit for bit, and the solve matches the one with 25-iteration chunks throughout."""
+    dims = (16, 16, 16, 32)
+    U = li.near_identity_links(dims, 0.3, 207)
+    b = to_dev(li.gaussian_even_source(dims, 208))
+    G = gauge(dims, U, "f32", 12)
+    x1, s1 = sp.cg_solve(G, 0.05, b, tol=1e-10, inner="f32", use_graph=True)
+    x2, s2 = sp.cg_solve(G, 0.05, b, tol=1e-10, inner="f32", use_graph=False)
+    x3, s3 = sp.cg_solve(G, 0.05, b, tol=1e-10, inner="f32", poll_chunk=25)
+    announce(f"tail chunks: iters {s1.iters} / {s2.iters} (25 throughout: {s3.iters}), ru {s1.reliable_updates}")
+    assert s1.converged and s1.iters == s2.iters and torch.equal(x1, x2)
+    assert s3.converged and rel_err_2(to_host(x1), to_host(x3)) <= 1e-6
+
+
+def test_graph_cache_trimmed_between_solves():
+    """More distinct solve set-ups than the graph cache holds (each workspace at its own address makes its graphs
+    distinct): the cache is emptied before a solve takes its graphs, never between the graphs of one solve, and
+    every solve still equals the eager one bit for bit."""
+    dims = (4, 4, 4, 8)
+    U = li.near_identity_links(dims, 0.3, 209)
+    b = to_dev(li.gaussian_even_source(dims, 210))
+    G = gauge(dims, U, "f32", 12)
+    xr, sr = sp.cg_solve(G, 0.1, b, tol=1e-8, inner="f32", use_graph=False, workspace=sp.Workspace())
+    keep = []
+    for k in range(45):
+        ws = sp.Workspace()
+        keep.append(ws)
+        x, st = sp.cg_solve(G, 0.1, b, tol=1e-8, inner="f32", workspace=ws)
+        assert st.converged and st.iters == sr.iters and torch.equal(x, xr), k
+    announce(f"graph cache: 45 set-ups, {sr.iters} iterations each")
+
+
 def test_warm_start():
     dims = (8, 8, 8, 8)
     U = li.near_identity_links(dims, 0.3, 205)
