@@ -324,14 +324,29 @@ def test_full_system_solve_rejects_zero_mass():
 
 @pytest.mark.parametrize("inner,recon", [("f32", 12), ("f16", 12)])
 def test_control_lattice_true_residual_through_the_operator(inner, recon):
-    """32^3x64 (beyond the Infinity Cache; no fused single-system iteration, so the finalize path runs), solved to
-    1e-8; the true residual |b - A x| / |b| is recomputed with the FP64 half operator entry point, independently of
-    the solver's own reliable-update residual."""
+    """32^3x64 (beyond the Infinity Cache; 4,096 blocks, whose fused launches sum 16 block partials per thread
+    before the operator), solved to 1e-8; the true residual |b - A x| / |b| is recomputed with the FP64 half
+    operator entry point, independently of the solver's own reliable-update residual."""
     dims = (32, 32, 32, 64)
     announce(f"control lattice {dims} {inner} r{recon}")
     lat = sp.Lattice(dims)
     links, b = _gpu_links_and_source(lat, 71)
     _solve_and_check_operator_residual(lat, links, b, inner, recon)
+
+
+@pytest.mark.parametrize("dims", [(32, 32, 16, 32), (32, 32, 16, 34)])
+def test_partial_sums_either_side_of_the_early_load_limit(dims):
+    """The fused launches load a thread's block partials before the operator's gathers when there are at most
+    four per thread (1,024 blocks of 256 threads: 32x32x16x32) and sum them all first beyond that (1,088 blocks:
+    32x32x16x34). Both solve to 1e-8 with the residual recomputed by the FP64 operator, and graph replay equals
+    eager launches bit for bit."""
+    lat = sp.Lattice(dims)
+    announce(f"partial-sum paths {dims}: {lat.Vh // 256} blocks")
+    links, b = _gpu_links_and_source(lat, 73)
+    G = _solve_and_check_operator_residual(lat, links, b, "f32", 12)
+    x1, s1 = sp.cg_solve(G, 0.01, b, tol=1e-8, inner="f32", use_graph=True)
+    x2, s2 = sp.cg_solve(G, 0.01, b, tol=1e-8, inner="f32", use_graph=False)
+    assert s1.iters == s2.iters and torch.equal(x1, x2)
 
 
 def _gpu_links_and_source(lat, seed):
