@@ -28,7 +28,7 @@ HBM_PEAK_GBS = 8000.0
 FLOP_PER_SITE = 570  # one half-Dslash output site: 8 SU(3) mat-vecs (66) + 7 colour-vector adds (6)
 # algorithmic bytes per output site of one half-Dslash: 8 links + 1 input vector (perfect neighbour
 # reuse) + 1 output vector
-LINK_BYTES = {("f64", 18): 144, ("f32", 18): 72, ("f32", 12): 48, ("f16", 18): 36, ("f16", 12): 24,
+LINK_BYTES = {("f64", 18): 144, ("f32", 18): 72, ("f32", 12): 48, ("f32", 8): 32, ("f16", 18): 36, ("f16", 12): 24,
               ("bf16", 18): 36, ("bf16", 12): 24, ("i16", 18): 36, ("i16", 12): 24}
 VEC_BYTES = {"f64": 48, "f32": 24, "f16": 16, "bf16": 12}
 
@@ -570,9 +570,9 @@ def bench_packing(sp, torch, lat, links, b, inner, recon, stream, log):
         t = e0.elapsed_time(e1) / 1e3 / n
         out[name] = {"us": t * 1e6, "bytes": nbytes, "hbm_frac": nbytes / t / 1e9 / HBM_PEAK_GBS}
     log("packing: " + ", ".join(f"{k} {v['us']:.1f} us" for k, v in out.items()))
-    out["note"] = ("natural complex128 input already in HBM; the recon-12 packing reads whole links (the dropped "
-                   "row shares their cache lines); the vector calls are short enough that the rate of the Python "
-                   "calls, not the kernel, sets their time")
+    out["note"] = ("natural complex128 input already in HBM; the recon-12 and recon-8 packings read whole links "
+                   "(the dropped entries share their cache lines); the vector calls are short enough that the rate "
+                   "of the Python calls, not the kernel, sets their time")
     return out
 
 
@@ -593,8 +593,10 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--inner", default="f32", choices=["f32", "f16", "bf16"])
-    ap.add_argument("--recon", type=int, default=12, choices=[18, 12],
-                    help="link storage: 12 = first two rows, third rebuilt as conj(row0 x row1) (exact for SU(3))")
+    ap.add_argument("--recon", type=int, default=12, choices=[18, 12, 8],
+                    help="link storage: 12 = first two rows, third rebuilt as conj(row0 x row1) (exact for SU(3)); "
+                         "8 = U01, U02, U10 and two phases, the rest rebuilt from unitarity (FP32 links only, "
+                         "entries good to about 1e-5)")
     ap.add_argument("--links", default=None, choices=["f16", "bf16", "i16"],
                     help="store the links of the timed solve in 16 bits (FP32 vectors; --inner f32 only)")
     ap.add_argument("--dims", type=int, nargs=4, default=[20, 20, 20, 64])
@@ -739,8 +741,8 @@ def main():
     bps = 8 * LINK_BYTES[(lprec, args.recon)] + 2 * VEC_BYTES[args.inner]
     alg_bytes = bps * lat.Vh
     flush = Flush(sp, torch, dev)
-    # both link-load policies of the tuned launch: warm (back-to-back; the 20^3x64 links, 98 MB in FP32
-    # recon-12, stay in the Infinity Cache, the solver's situation) and cold (each launch after a 1 GiB read
+    # both link-load policies of the tuned launch: warm (back-to-back; the 20^3x64 links, 66-98 MB in FP32
+    # recon-8 or recon-12, stay in the Infinity Cache, the solver's situation) and cold (each launch after a 1 GiB read
     # that flushes the Infinity Cache, net of the flush: every byte from HBM, the roofline figure)
     key = tune_key(dims, lprec, args.recon, args.inner)
     tuned = tuned_entry(args.tune_file, key)
@@ -778,7 +780,7 @@ def main():
         clinks = control_links(cd, 0.3, 51, dev, torch)
         cv = torch.randn(clat.Vh, 3, dtype=torch.complex128, device=dev)
         ctl = {}
-        for rc in (18, 12):
+        for rc in (18, 12) + ((8,) if args.inner == "f32" else ()):
             Gc = sp.Gauge(clat, clinks, lo_prec=args.inner, recon=rc)
             ci = sp.pack_vec(clat, cv, args.inner)
             co = torch.empty_like(ci)
@@ -808,13 +810,41 @@ def main():
             del Ga, ai, ao
         dslash_extra["all_packings"] = allc
         log("all packings: " + ", ".join(f"{kk} {vv['us']:.1f} us" for kk, vv in allc.items()))
-        extra_shard = bench_shard_share(sp, torch, dims, G64_links(), b, args.inner, args.recon, stream, log)
+        # the halo-fed operator is built for recon 18 and 12
+        extra_shard = bench_shard_share(sp, torch, dims, G64_links(), b, args.inner, min(max(args.recon, 12), 18),
+                                        stream, log)
         dslash_extra["shard_share"] = extra_shard
     del flush
 
     traffic = measured_traffic(args.inner, args.recon, dims, best_pol)
 
+    t_r12 = t_mixed if (args.inner, args.recon, args.links) == ("f32", 12, None) else None
     if not args.no_extras and "err_mixed_vs_fp64_1e12" in extra:
+        # FP32 iterations on the other link packings, same workload (recon 8: a third fewer link bytes, entries
+        # rebuilt to about 1e-5, which the reliable updates absorb)
+        f32c = {}
+        if args.inner == "f32" and not args.links:
+            for rc in (8, 12, 18):
+                if rc == args.recon:
+                    continue
+                Gr = sp.Gauge(lat, G64_links(), lo_prec="f32", recon=rc)
+                sp.cg_solve(Gr, mass, b, tol=tol, inner="f32", workspace=ws)
+                torch.cuda.synchronize()
+                pr, (xr_, str_) = timed_solves(
+                    torch, lambda: sp.cg_solve(Gr, mass, b, tol=tol, inner="f32", workspace=ws), max(1, args.steps))
+                tr, tr_se = mean_stderr(pr)
+                ib = iteration_bytes_per_site("f32", rc)
+                f32c[f"f32_r{rc}"] = {"s": tr, "s_stderr": tr_se, "solves": len(pr), "iters": str_.iters,
+                                      "reliable_updates": str_.reliable_updates, "true_rel_resid": str_.true_rel_resid,
+                                      "err_vs_fp64_1e12": float(torch.linalg.norm(xr_ - xref) / torch.linalg.norm(xref)),
+                                      "err_vs_oracle_samples": golden_err(xr_, dims, mass),
+                                      "speedup_vs_headline": t_mixed / tr, "iteration_bytes_per_site": ib,
+                                      "iteration_hbm_frac": ib * lat.Vh * str_.iters / tr / 1e9 / HBM_PEAK_GBS}
+                log(f"f32 r{rc}: {tr * 1e3:.2f} ms/solve iters={str_.iters}")
+                if rc == 12:
+                    t_r12 = tr
+                del Gr
+            extra["f32_other_recon"] = f32c
         # 16-bit storage of links and vectors with FP32 arithmetic, same workload
         low = {}
         for prec in ("f16", "bf16"):
@@ -831,7 +861,9 @@ def main():
                                         "reliable_updates": stl.reliable_updates,
                                         "true_rel_resid": stl.true_rel_resid, "err_vs_fp64_1e12": el,
                                         "err_vs_oracle_samples": golden_err(xl, dims, mass),
-                                        "speedup_vs_inner": t_mixed / tl, "iteration_bytes_per_site": ib,
+                                        "speedup_vs_inner": t_mixed / tl,
+                                        "speedup_vs_f32_r12": t_r12 / tl if t_r12 else None,
+                                        "iteration_bytes_per_site": ib,
                                         "iteration_hbm_frac": ib * lat.Vh * stl.iters / tl / 1e9 / HBM_PEAK_GBS}
                 log(f"{prec} r{rc}: {tl * 1e3:.2f} ms/solve iters={stl.iters} err={el:.2e}")
                 del Gl
@@ -853,6 +885,7 @@ def main():
                                             "true_rel_resid": stl.true_rel_resid, "err_vs_fp64_1e12": el,
                                             "err_vs_oracle_samples": golden_err(xl, dims, mass),
                                             "speedup_vs_inner": t_mixed / tl,
+                                            "speedup_vs_f32_r12": t_r12 / tl if t_r12 else None,
                                             "iteration_bytes_per_site": ib,
                                             "iteration_hbm_frac": ib * lat.Vh / (tl / max(stl.iters, 1)) / 1e9 / HBM_PEAK_GBS}
                 log(f"links {lp} r{rc} + f32 vectors: {tl * 1e3:.2f} ms/solve iters={stl.iters} err={el:.2e}")

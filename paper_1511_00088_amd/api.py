@@ -73,6 +73,12 @@ def pack_gauge(lat: Lattice, links: torch.Tensor, prec, recon: int = 18) -> torc
     nbytes = lat.gauge_bytes(prec, recon)
     if nbytes == 0:
         raise ValueError(f"unsupported packing prec={prec} recon={recon}")
+    if int(recon) == 8:
+        # recon 8 rebuilds the lower 2x2 block by dividing by n = |U01|^2 + |U02|^2: a link whose first row is a
+        # phase times (1, 0, 0) has n = 0 and cannot be stored this way
+        n = links[..., 0, 1].abs().square() + links[..., 0, 2].abs().square()
+        if bool((n == 0).any()):
+            raise ValueError("recon 8 cannot store links whose first row is a phase times (1, 0, 0)")
     out = torch.empty(nbytes, dtype=torch.uint8, device=links.device)
     L.check(L.load().sp_gauge_pack(ctypes.byref(lat.geom), _ptr(links), _prec(prec), int(recon), _ptr(out),
                                    _stream()), "sp_gauge_pack")
@@ -80,7 +86,8 @@ def pack_gauge(lat: Lattice, links: torch.Tensor, prec, recon: int = 18) -> torc
 
 
 class Gauge:
-    """A gauge field packed for the GPU: FP64 (recon 18) plus an optional low-precision packing."""
+    """A gauge field packed for the GPU: FP64 (recon 18) plus an optional low-precision packing (recon 18, 12, or
+    8 for FP32 links)."""
 
     def __init__(self, lat: Lattice, links: torch.Tensor, lo_prec="f32", recon: int = 18):
         self.lat = lat

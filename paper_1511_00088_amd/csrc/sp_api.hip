@@ -152,7 +152,7 @@ int check_geom(const sp_geom* g, Geom* out) {
 
 size_t link_bytes(int prec, int recon) {
     if (prec == SP_F64) return recon == 18 ? 144 : 0;
-    if (prec == SP_F32) return recon == 18 ? 72 : recon == 12 ? 48 : 0;
+    if (prec == SP_F32) return recon == 18 ? 72 : recon == 12 ? 48 : recon == 8 ? 32 : 0;
     if (prec == SP_F16 || prec == SP_BF16 || prec == SP_I16) return recon == 18 ? 36 : recon == 12 ? 24 : 0;
     return 0;
 }
@@ -365,7 +365,9 @@ int check_gauge(const sp_gauge* U, int inner) {
     const bool links_ok = U->lo_prec == inner || (inner == SP_F32 && is_16bit_link(U->lo_prec));
     if (!links_ok)
         return fail(SP_ERR_UNSUPPORTED, "gauge lo precision %d cannot serve inner precision %d", U->lo_prec, inner);
-    if (U->recon != 18 && U->recon != 12) return fail(SP_ERR_INVALID_ARG, "recon must be 18 or 12");
+    if (U->recon != 18 && U->recon != 12 && U->recon != 8)
+        return fail(SP_ERR_INVALID_ARG, "recon must be 18, 12 or 8");
+    if (U->recon == 8 && U->lo_prec != SP_F32) return fail(SP_ERR_UNSUPPORTED, "recon 8 is built for FP32 links only");
     return SP_OK;
 }
 
@@ -981,7 +983,10 @@ static int dslash_desc(const sp_geom* g, const sp_gauge* U, int prec, const void
     } else {
         const bool links_ok = U->lo_prec == prec || (prec == SP_F32 && is_16bit_link(U->lo_prec));
         if (!links_ok) return fail(SP_ERR_UNSUPPORTED, "gauge lo precision %d with vectors of precision %d", U->lo_prec, prec);
-        if (U->recon != 18 && U->recon != 12) return fail(SP_ERR_INVALID_ARG, "recon must be 18 or 12");
+        if (U->recon != 18 && U->recon != 12 && U->recon != 8)
+            return fail(SP_ERR_INVALID_ARG, "recon must be 18, 12 or 8");
+        if (U->recon == 8 && U->lo_prec != SP_F32)
+            return fail(SP_ERR_UNSUPPORTED, "recon 8 is built for FP32 links only");
         links = U->lo;
         *lp = U->lo_prec;
         *recon = U->recon;

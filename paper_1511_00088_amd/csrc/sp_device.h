@@ -334,6 +334,7 @@ __device__ __forceinline__ uint32_t ldw(const uint32_t* p) {
 //   F64  r18: 9 planes double2                         144 B/link
 //   F32  r18: 4 planes float4 + 1 plane float2          72 B/link
 //   F32  r12: 3 planes float4 (rows 0,1)                48 B/link
+//   F32  r8 : 2 planes float4 (U01, U02; U10, 2 phases) 32 B/link
 //   16b  r18: 2 planes uint4 (16 values) + 1 plane uint  36 B/link
 //   16b  r12: 1 plane uint4 + 1 plane uint2             24 B/link
 // Real parts and imaginary parts alternate, row-major: e00.re e00.im e01.re ... e22.im.
@@ -401,6 +402,62 @@ template <>
 struct LinkFmt<F32, 18> : LinkFmtF32<18> {};
 template <>
 struct LinkFmt<F32, 12> : LinkFmtF32<12> {};
+
+// FP32 recon 8: plane 0 holds (U01, U02) and plane 1 (U10, arg U00, arg U20), 32 B per link. With
+// n = |U01|^2 + |U02|^2 the moduli follow from the unit norms of row 0 and column 0, |U00| = sqrt(1 - n) and
+// |U20| = sqrt(n - |U10|^2), and the four remaining entries from row 1 and row 2 being orthogonal to row 0 with
+// det U = 1 (each row the conjugate cross product of the other two), two 2x2 systems of determinant -n and n:
+//   U11 = -(conj U20 conj U02 + U01 U10 conj U00) / n,   U12 = (conj U01 conj U20 - U02 U10 conj U00) / n,
+//   U21 = (conj U10 conj U02 - U01 U20 conj U00) / n,    U22 = -(U02 U20 conj U00 + conj U01 conj U10) / n.
+// Every product is of stored or rebuilt entries of size <= sqrt(n) against the divisor n, so small n costs no
+// precision; n = 0 (row 0 a phase times (1, 0, 0)) leaves the lower block undetermined, and such fields are
+// refused when packed from Python (the C packing's caller must not pass them: the operator would be NaN and the
+// solve would stop with a breakdown). The phases go through the hardware sine and cosine and |U20| through a
+// difference of squares, so entries carry errors up to about 1e-5 where |U20| << |U10| (the operator's largest
+// element error on the 20^3x64 field: 1.4e-5 of its largest output), which the FP64 reliable updates absorb.
+template <>
+struct LinkFmt<F32, 8> {
+    static constexpr int bytes = 32;
+    template <bool NT = false>
+    __device__ static Su3<float> load(const void* blk, int Vh, int cb) {
+        using Cf = Cx<float>;
+        const float4* p = (const float4*)blk;
+        const float4 u = ldw<NT>(p + cb);
+        const float4 v = ldw<NT>(p + (size_t)Vh + cb);
+        const Cf a2 = {u.x, u.y}, a3 = {u.z, u.w}, b1 = {v.x, v.y};
+        const float n = a2.re * a2.re + a2.im * a2.im + a3.re * a3.re + a3.im * a3.im;
+        const float ra1 = sqrtf(fmaxf(1.0f - n, 0.0f));
+        const float rc1 = sqrtf(fmaxf(n - (b1.re * b1.re + b1.im * b1.im), 0.0f));
+        float s1, k1, s2, k2;
+        __sincosf(v.z, &s1, &k1);
+        __sincosf(v.w, &s2, &k2);
+        const Cf a1 = {ra1 * k1, ra1 * s1}, c1 = {rc1 * k2, rc1 * s2};
+        const float inv = 1.0f / n;
+        auto mul = [](Cf x, Cf y) { return Cf{x.re * y.re - x.im * y.im, x.re * y.im + x.im * y.re}; };
+        auto cj = [](Cf x) { return Cf{x.re, -x.im}; };
+        const Cf b1a = mul(b1, cj(a1)), c1a = mul(c1, cj(a1));
+        const Cf t1 = mul(cj(c1), cj(a3)), t2 = mul(a2, b1a), t3 = mul(cj(a2), cj(c1)), t4 = mul(a3, b1a);
+        const Cf t5 = mul(cj(b1), cj(a3)), t6 = mul(a2, c1a), t7 = mul(a3, c1a), t8 = mul(cj(a2), cj(b1));
+        Su3<float> U;
+        U.e[0][0] = a1;
+        U.e[0][1] = a2;
+        U.e[0][2] = a3;
+        U.e[1][0] = b1;
+        U.e[1][1] = {-(t1.re + t2.re) * inv, -(t1.im + t2.im) * inv};
+        U.e[1][2] = {(t3.re - t4.re) * inv, (t3.im - t4.im) * inv};
+        U.e[2][0] = c1;
+        U.e[2][1] = {(t5.re - t6.re) * inv, (t5.im - t6.im) * inv};
+        U.e[2][2] = {-(t7.re + t8.re) * inv, -(t7.im + t8.im) * inv};
+        return U;
+    }
+    // r: the 18 reals of the link, row-major, re and im alternating; the phases in FP64, then rounded
+    __device__ static void store(void* blk, int Vh, int cb, const double* r) {
+        float4* p = (float4*)blk;
+        p[cb] = make_float4((float)r[2], (float)r[3], (float)r[4], (float)r[5]);
+        p[(size_t)Vh + cb] =
+            make_float4((float)r[6], (float)r[7], (float)atan2(r[1], r[0]), (float)atan2(r[13], r[12]));
+    }
+};
 
 template <int P, int RECON>
 struct LinkFmt16 {
@@ -521,11 +578,11 @@ __host__ __device__ __forceinline__ float eta_sign(const Site& s, int mu) {
 }
 
 // Directions whose gathers a single-system half operator keeps in flight together (the unroll of its direction
-// loop), by measurement: two where all four put too many values in registers (FP64: 384 values; FP32 recon-12 and
-// 16-bit links with FP32 vectors: the row rebuild and the unpacking lower the waves per SIMD) unless the links
-// stream past the caches, four otherwise.
+// loop), by measurement: two where all four put too many values in registers (FP64: 384 values; FP32 recon-12
+// and recon-8 and 16-bit links with FP32 vectors: the rebuild of rows and the unpacking lower the waves per SIMD)
+// unless the links stream past the caches, four otherwise.
 constexpr int unroll_dirs(int lp, int recon, int vp, bool nt) {
-    return (vp == F64 || (!nt && ((lp == F32 && recon == 12) || (vp == F32 && lp != F32)))) ? 2 : 4;
+    return (vp == F64 || (!nt && ((lp == F32 && recon != 18) || (vp == F32 && lp != F32)))) ? 2 : 4;
 }
 
 // ------------------------------------------------------------------------------------------------------

@@ -113,6 +113,7 @@ hipError_t launch_pack_gauge(const Geom& g, const double* nat, int prec, int rec
     if (prec == F64 && recon == 18) SP_LAUNCH(F64, 18);
     if (prec == F32 && recon == 18) SP_LAUNCH(F32, 18);
     if (prec == F32 && recon == 12) SP_LAUNCH(F32, 12);
+    if (prec == F32 && recon == 8) SP_LAUNCH(F32, 8);
     if (prec == F16 && recon == 18) SP_LAUNCH(F16, 18);
     if (prec == F16 && recon == 12) SP_LAUNCH(F16, 12);
     if (prec == BF16 && recon == 18) SP_LAUNCH(BF16, 18);

@@ -46,6 +46,7 @@ hipError_t launch_dslash(const D& d, int nblocks, LaunchCfg c, int lp, int recon
     if (lp == F64 && recon == 18 && vp == F64) SP_LAUNCH(F64, 18, F64);
     if (lp == F32 && recon == 18 && vp == F32) SP_LAUNCH(F32, 18, F32);
     if (lp == F32 && recon == 12 && vp == F32) SP_LAUNCH(F32, 12, F32);
+    if (lp == F32 && recon == 8 && vp == F32) SP_LAUNCH(F32, 8, F32);
     if (lp == F16 && recon == 18 && vp == F16) SP_LAUNCH(F16, 18, F16);
     if (lp == F16 && recon == 12 && vp == F16) SP_LAUNCH(F16, 12, F16);
     if (lp == BF16 && recon == 18 && vp == BF16) SP_LAUNCH(BF16, 18, BF16);
@@ -77,6 +78,7 @@ hipError_t launch_norm_rec(const DescSingle& d, SolverState* st_out, int nblocks
     if (lp == F64 && recon == 18 && vp == F64) SP_LAUNCH(F64, 18, F64);
     if (lp == F32 && recon == 18 && vp == F32) SP_LAUNCH(F32, 18, F32);
     if (lp == F32 && recon == 12 && vp == F32) SP_LAUNCH(F32, 12, F32);
+    if (lp == F32 && recon == 8 && vp == F32) SP_LAUNCH(F32, 8, F32);
     if (lp == F16 && recon == 12 && vp == F32) SP_LAUNCH(F16, 12, F32);
     if (lp == F16 && recon == 18 && vp == F32) SP_LAUNCH(F16, 18, F32);
     if (lp == BF16 && recon == 12 && vp == F32) SP_LAUNCH(BF16, 12, F32);

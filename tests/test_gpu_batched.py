@@ -29,7 +29,7 @@ def _batch(inner, recon=18):
     return systems, host
 
 
-@pytest.mark.parametrize("inner,recon", [("f32", 18), ("f32", 12), ("f16", 18), ("bf16", 12), ("f64", 18)])
+@pytest.mark.parametrize("inner,recon", [("f32", 18), ("f32", 12), ("f32", 8), ("f16", 18), ("bf16", 12), ("f64", 18)])
 def test_batched_matches_oracle_and_single(inner, recon):
     announce(f"batched {inner} r{recon}")
     systems, host = _batch(inner, recon)

@@ -16,7 +16,14 @@ from gpu_common import DSLASH_TOL, announce, gauge, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
-COMBOS = [("f64", 18), ("f32", 18), ("f32", 12), ("f16", 18), ("f16", 12), ("bf16", 18), ("bf16", 12)]
+COMBOS = [("f64", 18), ("f32", 18), ("f32", 12), ("f32", 8), ("f16", 18), ("f16", 12), ("bf16", 18), ("bf16", 12)]
+
+
+def _tol(prec, recon):
+    """The gate per packing. FP32 recon 8 rebuilds U00 and U20 from FP32 phases (hardware sine and cosine) and
+    |U20| as a square root of a difference of squares, which loses precision where |U20| << |U10|: entries
+    good to about 1e-5 on these fields (the 20^3x64 operator's largest element error was 1.4e-5), gated at 1e-4."""
+    return 1e-4 if recon == 8 else DSLASH_TOL[prec]
 
 
 @pytest.mark.parametrize("prec,recon", COMBOS)
@@ -33,7 +40,7 @@ def test_dslash_parity_small(prec, recon, dims, bc_t):
         ref = oracle.dslash_eo(dims, U, xin, p, bc_t=bc_t)
         err = rel_err_max(y, ref)
         announce(f"  parity {p}: max rel err {err:.3e}")
-        assert err <= DSLASH_TOL[prec], (prec, recon, p, err)
+        assert err <= _tol(prec, recon), (prec, recon, p, err)
 
 
 @pytest.mark.parametrize("prec,recon", COMBOS)
@@ -54,7 +61,7 @@ def test_dslash_parity_cfg1_sampled(prec, recon):
         ref = oracle.dslash_eo_sites(dims, U, xin, p, cbs)
         err = rel_err_max(y, ref)
         announce(f"  parity {p}: sampled max rel err {err:.3e}")
-        assert err <= DSLASH_TOL[prec]
+        assert err <= _tol(prec, recon)
 
 
 _CACHE = {}
@@ -64,6 +71,15 @@ def _cfg1_links():
     if "U" not in _CACHE:
         _CACHE["U"] = li.near_identity_links((20, 20, 20, 64), 0.3, 21)
     return _CACHE["U"]
+
+
+def test_recon8_refuses_links_without_off_diagonal_first_row():
+    """Recon 8 divides by |U01|^2 + |U02|^2; the unit field has it 0 everywhere and is refused when packed."""
+    dims = (4, 4, 4, 4)
+    U = np.zeros((4, li.volume(dims), 3, 3), dtype=np.complex128)
+    U[..., 0, 0] = U[..., 1, 1] = U[..., 2, 2] = 1.0
+    with pytest.raises(ValueError):
+        gauge(dims, U, "f32", 8)
 
 
 def test_pack_roundtrip():
