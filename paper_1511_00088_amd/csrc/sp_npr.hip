@@ -71,14 +71,58 @@ __device__ __forceinline__ void path_ld(const Paths& P, int X, int Y, C (&m)[3][
     for (int j = 0; j < 9; ++j) m[j / 3][j % 3] = {P[j][q].x, P[j][q].y};
 }
 
+// The pairs at corner distance LEVEL (2, 3 or 4), each U_AD the average over the LEVEL directions mu in which A
+// and D differ of L(A -> A^mu) U_{A^mu, D} (see build_paths). The work is cut into items of NC columns of one row
+// of one pair (NC = 3: a row; NC = 1: one element), numbered with A fastest, so the 16 lanes of a quarter
+// wavefront share the corner difference, the row and the columns and differ in A: their reads of U_{A, A^mu}
+// and U_{A^mu, D} and their writes of U_{A, D} fall in distinct LDS banks (sp_npr_layout.h). Every lane takes
+// the set bits of its difference in increasing order, so all lanes run the same LEVEL steps and the products
+// are summed in the same order whatever the cut.
+template <int LEVEL, int NC>
+__device__ __forceinline__ void path_level(Paths& P) {
+    // the corner differences with LEVEL bits set, in increasing order, four bits each
+    constexpr int nd = LEVEL == 2 ? 6 : LEVEL == 3 ? 4 : 1;
+    constexpr unsigned tab = LEVEL == 2 ? 0xCA9653u : LEVEL == 3 ? 0xEDB7u : 0xFu;
+    constexpr int per = 9 / NC;  // items per pair
+    const double w = 1.0 / LEVEL;
+    for (int it = threadIdx.x; it < 16 * nd * per; it += 256) {
+        const int A = it & 15, sub = (it >> 4) % per, diff = (tab >> (4 * ((it >> 4) / per))) & 15, D = A ^ diff;
+        const int i = sub * NC / 3, j0 = (sub * NC) % 3;
+        C acc[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) acc[c] = {0.0, 0.0};
+        int left = diff;
+#pragma unroll
+        for (int k = 0; k < LEVEL; ++k) {
+            const int mu = __builtin_ctz(left);
+            left &= left - 1;
+            const int A1 = A ^ (1 << mu), ql = ppos(A, A1), qr = ppos(A1, D);
+            C L[3];
+#pragma unroll
+            for (int k2 = 0; k2 < 3; ++k2) L[k2] = {P[i * 3 + k2][ql].x, P[i * 3 + k2][ql].y};
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                const int j = j0 + c;
+                const C R0 = {P[j][qr].x, P[j][qr].y}, R1 = {P[3 + j][qr].x, P[3 + j][qr].y},
+                        R2 = {P[6 + j][qr].x, P[6 + j][qr].y};
+                acc[c] = cmac(cmac(cmac(acc[c], L[0], R0), L[1], R1), L[2], R2);
+            }
+        }
+        const int q = ppos(A, D);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) P[i * 3 + j0 + c][q] = make_double2(w * acc[c].re, w * acc[c].im);
+    }
+    __syncthreads();
+}
+
 // The path links of hypercube z into P (LDS), by the 256 threads of a block. The average over the k! shortest
 // paths is built from the first step: U_AD = (1/k) sum over the k directions mu in which A and D differ of
 // L(A -> A^mu) U_{A^mu, D}, where L(A -> A^mu) = U_{A, A^mu} is U_mu(z_A) when A_mu = 0 and U_mu(z_A - mu)^dag
 // otherwise. Distance 0 is the identity and distance 1 the hypercube's 32 links and their conjugate transposes,
 // stored straight from memory; pairs at distance 2, 3, 4 follow in that order, so every U_{A^mu, D} and
-// U_{A, A^mu} a thread needs is complete one barrier earlier. A thread forms one pair's average at distances 2
-// and 3 (96 and 64 pairs) and one row of it at distance 4, so that the 16 pairs there, whose averages have the
-// most terms, do not run on 16 threads alone. Ends with a barrier.
+// U_{A, A^mu} a thread needs is complete one barrier earlier. Distances 2 and 4 are cut into single elements
+// (864 and 144 items over the 256 threads), distance 3 into rows (192 items), which keeps each level's longest
+// chain of products short. Ends with a barrier.
 __device__ __forceinline__ void build_paths(const NprGeom& g, const double2* __restrict__ U, int z, Paths& P) {
     const int t = threadIdx.x;
     int zc[4];
@@ -97,47 +141,9 @@ __device__ __forceinline__ void build_paths(const NprGeom& g, const double2* __r
 #pragma unroll
         for (int j = 0; j < 9; ++j) P[j][ppos(t, t)] = make_double2(j % 4 == 0 ? 1.0 : 0.0, 0.0);
     __syncthreads();
-    for (int level = 2; level <= 4; ++level) {
-        // the corner differences with level bits set, in increasing order, four bits each
-        const int nd = level == 2 ? 6 : level == 3 ? 4 : 1;
-        const unsigned tab = level == 2 ? 0xCA9653u : level == 3 ? 0xEDB7u : 0xFu;
-        const double w = 1.0 / level;
-        // distances 2 and 3: one thread per pair (96 and 64 pairs); distance 4: one thread per row of a pair
-        const int rows = level == 4 ? 3 : 1;
-        if (t < 16 * nd * rows) {
-            const int pr = t % (16 * nd), A = pr / nd, diff = (tab >> (4 * (pr % nd))) & 15, D = A ^ diff;
-            const int r0 = level == 4 ? t / 16 : 0, r1 = level == 4 ? r0 + 1 : 3;
-            C acc[3][3];
-#pragma unroll
-            for (int i = 0; i < 3; ++i)
-#pragma unroll
-                for (int j = 0; j < 3; ++j) acc[i][j] = {0.0, 0.0};
-            for (int mu = 0; mu < 4; ++mu) {
-                if (!((diff >> mu) & 1)) continue;
-                const int A1 = A ^ (1 << mu), ql = ppos(A, A1), qr = ppos(A1, D);
-                C R[3][3];
-#pragma unroll
-                for (int j = 0; j < 9; ++j) R[j / 3][j % 3] = {P[j][qr].x, P[j][qr].y};
-#pragma unroll
-                for (int i = 0; i < 3; ++i) {
-                    if (i < r0 || i >= r1) continue;
-                    C L[3];
-#pragma unroll
-                    for (int k = 0; k < 3; ++k) L[k] = {P[i * 3 + k][ql].x, P[i * 3 + k][ql].y};
-#pragma unroll
-                    for (int j = 0; j < 3; ++j)
-                        acc[i][j] = cmac(cmac(cmac(acc[i][j], L[0], R[0][j]), L[1], R[1][j]), L[2], R[2][j]);
-                }
-            }
-            const int q = ppos(A, D);
-#pragma unroll
-            for (int i = 0; i < 3; ++i)
-                if (i >= r0 && i < r1)
-#pragma unroll
-                    for (int j = 0; j < 3; ++j) P[i * 3 + j][q] = make_double2(w * acc[i][j].re, w * acc[i][j].im);
-        }
-        __syncthreads();
-    }
+    path_level<2, 1>(P);
+    path_level<3, 3>(P);
+    path_level<4, 1>(P);
 }
 
 // One block per hypercube: the path links, written as one contiguous 36 KB block per hypercube (pair A * 16 + D,
