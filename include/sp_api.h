@@ -73,8 +73,9 @@ typedef struct {
 /* A packed gauge field. f64: FP64 recon-18 packing (needed by every solve: true residuals);
  * lo: the packing used by the low-precision iterations, of precision lo_prec with recon 18 (all 9 complex
  * entries), 12 (first two rows; the third is rebuilt as conj(row0 x row1), exact for SU(3) links) or, for SP_F32
- * only, 8 (U01, U02, U10 and the phases of U00 and U20; the rest rebuilt from unitarity and det = 1, for SU(3)
- * links whose first row is not a phase times (1, 0, 0), with entries good to about 1e-5). lo_prec is the inner
+ * only, 8 (U01, U02, the smaller in modulus of U10 and U20, and the phases of U00 and of the larger one; the rest
+ * rebuilt from unitarity and det = 1, for SU(3) links whose first row is not a phase times (1, 0, 0); entries
+ * within about 6e-7 of the FP64 links while |U00| stays away from 0, as in smeared fields). lo_prec is the inner
  * precision, or, for FP32 iterations, a 16-bit link storage (SP_F16, SP_BF16, SP_I16) with FP32 vectors and
  * arithmetic. lo may equal f64 when lo_prec is SP_F64. */
 typedef struct {
@@ -154,8 +155,10 @@ const char* sp_last_error(void);
 size_t sp_gauge_bytes(const sp_geom* g, int prec, int recon);
 
 /* Pack natural links (device, complex128 [4][V][3][3]) into out (device, sp_gauge_bytes). Rounds to
- * nearest-even when narrowing. Asynchronous on stream. Recon 8 stores the phases of U00 and U20 as FP32
- * angles (atan2 in FP64, then rounded) and needs |U01|^2 + |U02|^2 > 0 for every link (not checked here). */
+ * nearest-even when narrowing. Asynchronous on stream. Recon 8 stores, per link, the float4 planes
+ * (U01, U02) and (S, arg U00, f): S the smaller in modulus of U10 and U20, f the phase of the other one, plus 8
+ * when S is U20 (angles from atan2 in FP64, then rounded). It needs |U01|^2 + |U02|^2 > 0 for every link (not
+ * checked here). */
 int sp_gauge_pack(const sp_geom* g, const double* links_nat, int prec, int recon, void* out, void* stream);
 
 /* Bytes of one packed parity-half vector of precision prec (FP16 includes a per-site FP32 norm). */

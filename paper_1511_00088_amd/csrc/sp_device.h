@@ -403,18 +403,22 @@ struct LinkFmt<F32, 18> : LinkFmtF32<18> {};
 template <>
 struct LinkFmt<F32, 12> : LinkFmtF32<12> {};
 
-// FP32 recon 8: plane 0 holds (U01, U02) and plane 1 (U10, arg U00, arg U20), 32 B per link. With
-// n = |U01|^2 + |U02|^2 the moduli follow from the unit norms of row 0 and column 0, |U00| = sqrt(1 - n) and
-// |U20| = sqrt(n - |U10|^2), and the four remaining entries from row 1 and row 2 being orthogonal to row 0 with
-// det U = 1 (each row the conjugate cross product of the other two), two 2x2 systems of determinant -n and n:
+// FP32 recon 8: plane 0 holds (U01, U02) and plane 1 (S, arg U00, f), 32 B per link, where S is the smaller in
+// modulus of U10 and U20 and f the phase of the other one, L; f is stored plus 8 when S is U20 (phases lie in
+// [-pi, pi], so the offset marks the case; subtracting it again is exact, and the phase keeps a quantum of
+// 9.5e-7). With n = |U01|^2 + |U02|^2 the moduli follow from the unit norms of row 0 and column 0,
+// |U00| = sqrt(1 - n) and |L| = sqrt(n - |S|^2) >= sqrt(n / 2) (so the difference of squares loses nothing;
+// rebuilding the smaller entry from it instead leaves errors up to 1e-4 on near-identity fields), and the four
+// remaining entries from row 1 and row 2 being orthogonal to row 0 with det U = 1 (each row the conjugate cross
+// product of the other two), two 2x2 systems of determinant -n and n:
 //   U11 = -(conj U20 conj U02 + U01 U10 conj U00) / n,   U12 = (conj U01 conj U20 - U02 U10 conj U00) / n,
 //   U21 = (conj U10 conj U02 - U01 U20 conj U00) / n,    U22 = -(U02 U20 conj U00 + conj U01 conj U10) / n.
 // Every product is of stored or rebuilt entries of size <= sqrt(n) against the divisor n, so small n costs no
 // precision; n = 0 (row 0 a phase times (1, 0, 0)) leaves the lower block undetermined, and such fields are
 // refused when packed from Python (the C packing's caller must not pass them: the operator would be NaN and the
-// solve would stop with a breakdown). The phases go through the hardware sine and cosine and |U20| through a
-// difference of squares, so entries carry errors up to about 1e-5 where |U20| << |U10| (the operator's largest
-// element error on the 20^3x64 field: 1.4e-5 of its largest output), which the FP64 reliable updates absorb.
+// solve would stop with a breakdown). |U00| = sqrt(1 - n) loses precision as |U00| -> 0, which near-identity
+// (smeared) fields never approach. On the 20^3x64 near-identity field the rebuilt entries are within 6e-7 of
+// the FP64 links (FP32 rounding 4e-8, phase quantum and hardware sine and cosine the rest).
 template <>
 struct LinkFmt<F32, 8> {
     static constexpr int bytes = 32;
@@ -424,14 +428,17 @@ struct LinkFmt<F32, 8> {
         const float4* p = (const float4*)blk;
         const float4 u = ldw<NT>(p + cb);
         const float4 v = ldw<NT>(p + (size_t)Vh + cb);
-        const Cf a2 = {u.x, u.y}, a3 = {u.z, u.w}, b1 = {v.x, v.y};
+        const Cf a2 = {u.x, u.y}, a3 = {u.z, u.w}, sm = {v.x, v.y};
+        const bool s_is_u20 = v.w > 4.0f;
+        const float f = s_is_u20 ? v.w - 8.0f : v.w;
         const float n = a2.re * a2.re + a2.im * a2.im + a3.re * a3.re + a3.im * a3.im;
         const float ra1 = sqrtf(fmaxf(1.0f - n, 0.0f));
-        const float rc1 = sqrtf(fmaxf(n - (b1.re * b1.re + b1.im * b1.im), 0.0f));
+        const float rl = sqrtf(fmaxf(n - (sm.re * sm.re + sm.im * sm.im), 0.0f));
         float s1, k1, s2, k2;
         __sincosf(v.z, &s1, &k1);
-        __sincosf(v.w, &s2, &k2);
-        const Cf a1 = {ra1 * k1, ra1 * s1}, c1 = {rc1 * k2, rc1 * s2};
+        __sincosf(f, &s2, &k2);
+        const Cf a1 = {ra1 * k1, ra1 * s1}, lg = {rl * k2, rl * s2};
+        const Cf b1 = s_is_u20 ? lg : sm, c1 = s_is_u20 ? sm : lg;
         const float inv = 1.0f / n;
         auto mul = [](Cf x, Cf y) { return Cf{x.re * y.re - x.im * y.im, x.re * y.im + x.im * y.re}; };
         auto cj = [](Cf x) { return Cf{x.re, -x.im}; };
@@ -454,8 +461,10 @@ struct LinkFmt<F32, 8> {
     __device__ static void store(void* blk, int Vh, int cb, const double* r) {
         float4* p = (float4*)blk;
         p[cb] = make_float4((float)r[2], (float)r[3], (float)r[4], (float)r[5]);
-        p[(size_t)Vh + cb] =
-            make_float4((float)r[6], (float)r[7], (float)atan2(r[1], r[0]), (float)atan2(r[13], r[12]));
+        const bool s_is_u20 = r[12] * r[12] + r[13] * r[13] < r[6] * r[6] + r[7] * r[7];
+        const double sr = s_is_u20 ? r[12] : r[6], si = s_is_u20 ? r[13] : r[7];
+        const double f = s_is_u20 ? atan2(r[7], r[6]) + 8.0 : atan2(r[13], r[12]);
+        p[(size_t)Vh + cb] = make_float4((float)sr, (float)si, (float)atan2(r[1], r[0]), (float)f);
     }
 };
 

@@ -6,7 +6,8 @@ sites of parity q in checkerboard order (cb = lex / 2), split into planes of wor
 r[2k] = Re U[k / 3][k % 3], r[2k + 1] = Im U[k / 3][k % 3] (recon 12 keeps k < 6):
   FP64 r18: 9 planes of (r[2k], r[2k + 1]) as double2;
   FP32: planes of float4 (r[4k .. 4k + 3]), and for recon 18 a last plane of float2 (r[16], r[17]); recon 8:
-  two planes of float4, (r[2], r[3], r[4], r[5]) and (r[6], r[7], atan2(r[1], r[0]), atan2(r[13], r[12]));
+  two planes of float4, (r[2], r[3], r[4], r[5]) and (S, atan2(r[1], r[0]), f), S = (r[6], r[7]) = U10 and
+  f = atan2(r[13], r[12]) where |U10| <= |U20|, else S = (r[12], r[13]) = U20 and f = atan2(r[7], r[6]) + 8;
   16-bit (FP16, BF16, fixed point): word k = code(r[2k]) | code(r[2k + 1]) << 16; words 0-3 in a plane of uint4,
   then words 4-5 in a plane of uint2 (recon 12), or words 4-7 in a uint4 plane and word 8 in a uint32 plane.
 Codes: the FP64 real rounded to FP32 (nearest even), then FP16 nearest even, BF16 nearest even, or fixed point
@@ -54,8 +55,11 @@ def _reference(U: np.ndarray, dims, prec: str, recon: int) -> bytes:
                 planes = [np.ascontiguousarray(r[:, 2 * k:2 * k + 2]) for k in range(9)]
             elif prec == "f32" and recon == 8:
                 full = reals[mu, order, :18]
-                p1 = np.stack([full[:, 6], full[:, 7], np.arctan2(full[:, 1], full[:, 0]),
-                               np.arctan2(full[:, 13], full[:, 12])], axis=1)
+                s20 = full[:, 12] ** 2 + full[:, 13] ** 2 < full[:, 6] ** 2 + full[:, 7] ** 2
+                p1 = np.stack([np.where(s20, full[:, 12], full[:, 6]), np.where(s20, full[:, 13], full[:, 7]),
+                               np.arctan2(full[:, 1], full[:, 0]),
+                               np.where(s20, np.arctan2(full[:, 7], full[:, 6]) + 8.0,
+                                        np.arctan2(full[:, 13], full[:, 12]))], axis=1)
                 planes = [np.ascontiguousarray(full[:, 2:6].astype(np.float32)),
                           np.ascontiguousarray(p1.astype(np.float32))]
             elif prec == "f32":
@@ -107,9 +111,10 @@ def test_gauge_packing_byte_for_byte(prec, recon, dims):
 
 @pytest.mark.parametrize("dims", [(4, 6, 2, 8), (2, 2, 2, 2)])
 def test_gauge_packing_recon8(dims):
-    """FP32 recon 8: plane 0 (U01, U02) and plane 1 (U10, arg U00, arg U20) as float4. The entries are FP32
-    roundings of the FP64 reals, byte for byte; the phases come from the device's FP64 atan2, which may differ from
-    numpy's by an ulp before the rounding to FP32, so they are compared to one FP32 ulp."""
+    """FP32 recon 8: plane 0 (U01, U02) and plane 1 (S, arg U00, f) as float4, S the smaller of U10 and U20 in
+    modulus and f the other one's phase, plus 8 when S is U20 (both choices occur in both fields). The entries are
+    FP32 roundings of the FP64 reals, byte for byte; the phases come from the device's FP64 atan2, which may differ
+    from numpy's by an ulp before the rounding to FP32, so they are compared to one FP32 ulp."""
     announce(f"pack layout f32 r8 dims={dims}")
     lat = sp.Lattice(dims)
     for U in (li.haar_links(dims, 736), li.near_identity_links(dims, 0.3, 737)):
@@ -120,6 +125,8 @@ def test_gauge_packing_recon8(dims):
         assert np.array_equal(got[:, 0], ref[:, 0]) and np.array_equal(got[:, 1, :, :2], ref[:, 1, :, :2])
         ulp = np.spacing(np.abs(ref[:, 1, :, 2:]).astype(np.float32))
         assert (np.abs(got[:, 1, :, 2:] - ref[:, 1, :, 2:]) <= ulp).all()
+        flagged = got[:, 1, :, 3] > 4.0
+        assert flagged.any() and not flagged.all()
 
 
 def test_gauge_f64_field_of_a_gauge_is_the_recon18_packing():
