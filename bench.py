@@ -810,9 +810,9 @@ def main():
             del Ga, ai, ao
         dslash_extra["all_packings"] = allc
         log("all packings: " + ", ".join(f"{kk} {vv['us']:.1f} us" for kk, vv in allc.items()))
-        # the halo-fed operator is built for recon 18 and 12
-        extra_shard = bench_shard_share(sp, torch, dims, G64_links(), b, args.inner, min(max(args.recon, 12), 18),
-                                        stream, log)
+        # the halo-fed operator of the same packing (FP64 links are stored whole)
+        extra_shard = bench_shard_share(sp, torch, dims, G64_links(), b, args.inner,
+                                        18 if args.inner == "f64" else args.recon, stream, log)
         dslash_extra["shard_share"] = extra_shard
     del flush
 

@@ -355,7 +355,8 @@ int sp_face_pack(const sp_shard* s, int prec, const void* ext, int side, void* f
 int sp_face_unpack(const sp_shard* s, int prec, const void* face, int side, void* ext, void* stream);
 
 /* Bytes of the ghost t-links of a shard (U_t on global slice t0 - 1, both parities, 2F links) in the packed link
- * format of (prec, recon). */
+ * format of (prec, recon): recon 18 or 12, or 8 with SP_F32, as for sp_gauge_bytes; 0 for a combination that is
+ * not built. */
 size_t sp_shard_ghost_bytes(const sp_shard* s, int prec, int recon);
 
 /* Pack the ghost t-links: tlinks_nat = U_t(x, y, z, t0 - 1 mod T), device complex128 [X Y Z][3][3] in the order

@@ -68,17 +68,21 @@ class Lattice:
         return int(L.load().sp_gauge_bytes(ctypes.byref(self.geom), _prec(prec), int(recon)))
 
 
+def _refuse_recon8_singular(links: torch.Tensor) -> None:
+    """Recon 8 rebuilds the lower 2x2 block by dividing by n = |U01|^2 + |U02|^2: a link whose first row is a
+    phase times (1, 0, 0) has n = 0 and cannot be stored this way."""
+    n = links[..., 0, 1].abs().square() + links[..., 0, 2].abs().square()
+    if bool((n == 0).any()):
+        raise ValueError("recon 8 cannot store links whose first row is a phase times (1, 0, 0)")
+
+
 def pack_gauge(lat: Lattice, links: torch.Tensor, prec, recon: int = 18) -> torch.Tensor:
     _check_c128(links, (4, lat.V, 3, 3), "links")
     nbytes = lat.gauge_bytes(prec, recon)
     if nbytes == 0:
         raise ValueError(f"unsupported packing prec={prec} recon={recon}")
     if int(recon) == 8:
-        # recon 8 rebuilds the lower 2x2 block by dividing by n = |U01|^2 + |U02|^2: a link whose first row is a
-        # phase times (1, 0, 0) has n = 0 and cannot be stored this way
-        n = links[..., 0, 1].abs().square() + links[..., 0, 2].abs().square()
-        if bool((n == 0).any()):
-            raise ValueError("recon 8 cannot store links whose first row is a phase times (1, 0, 0)")
+        _refuse_recon8_singular(links)
     out = torch.empty(nbytes, dtype=torch.uint8, device=links.device)
     L.check(L.load().sp_gauge_pack(ctypes.byref(lat.geom), _ptr(links), _prec(prec), int(recon), _ptr(out),
                                    _stream()), "sp_gauge_pack")
@@ -414,6 +418,8 @@ class Shard:
         nbytes = self.ghost_bytes(prec, recon)
         if nbytes == 0:
             raise ValueError(f"unsupported packing prec={prec} recon={recon}")
+        if int(recon) == 8:
+            _refuse_recon8_singular(tlinks)
         out = torch.empty(nbytes, dtype=torch.uint8, device=tlinks.device)
         L.check(L.load().sp_shard_ghost_pack(ctypes.byref(self.struct), _ptr(tlinks), _prec(prec), int(recon),
                                              _ptr(out), _stream()), "sp_shard_ghost_pack")

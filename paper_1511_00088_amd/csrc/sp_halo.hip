@@ -210,6 +210,7 @@ hipError_t launch_pack_ghost(const Geom& g, int tb, const double* nat, int prec,
     if (prec == F64 && recon == 18) SP_LAUNCH(F64, 18);
     if (prec == F32 && recon == 18) SP_LAUNCH(F32, 18);
     if (prec == F32 && recon == 12) SP_LAUNCH(F32, 12);
+    if (prec == F32 && recon == 8) SP_LAUNCH(F32, 8);
     if (prec == F16 && recon == 18) SP_LAUNCH(F16, 18);
     if (prec == F16 && recon == 12) SP_LAUNCH(F16, 12);
     if (prec == BF16 && recon == 18) SP_LAUNCH(BF16, 18);
@@ -238,6 +239,7 @@ hipError_t launch_dslash_halo(const Shard& sh, int lp, int recon, int vp, const 
     if (lp == F64 && recon == 18 && vp == F64) SP_LAUNCH(F64, 18, F64);
     if (lp == F32 && recon == 18 && vp == F32) SP_LAUNCH(F32, 18, F32);
     if (lp == F32 && recon == 12 && vp == F32) SP_LAUNCH(F32, 12, F32);
+    if (lp == F32 && recon == 8 && vp == F32) SP_LAUNCH(F32, 8, F32);
     if (lp == F16 && recon == 18 && vp == F16) SP_LAUNCH(F16, 18, F16);
     if (lp == F16 && recon == 12 && vp == F16) SP_LAUNCH(F16, 12, F16);
     if (lp == BF16 && recon == 18 && vp == BF16) SP_LAUNCH(BF16, 18, BF16);
@@ -271,7 +273,7 @@ size_t vec_site_bytes_of(int prec) {
 
 size_t link_bytes_of(int prec, int recon) {
     if (prec == SP_F64) return recon == 18 ? 144 : 0;
-    if (prec == SP_F32) return recon == 18 ? 72 : recon == 12 ? 48 : 0;
+    if (prec == SP_F32) return recon == 18 ? 72 : recon == 12 ? 48 : recon == 8 ? 32 : 0;
     if (prec == SP_F16 || prec == SP_BF16 || prec == SP_I16) return recon == 18 ? 36 : recon == 12 ? 24 : 0;
     return 0;
 }
@@ -378,7 +380,10 @@ int sp_dslash_halo(const sp_shard* s, const sp_gauge* U, const void* ghost, int 
         const bool ok = U->lo_prec == prec ||
                         (prec == SP_F32 && (U->lo_prec == SP_F16 || U->lo_prec == SP_BF16 || U->lo_prec == SP_I16));
         if (!ok) return sp::set_error(SP_ERR_UNSUPPORTED, "gauge precision cannot serve these vectors");
-        if (U->recon != 18 && U->recon != 12) return sp::set_error(SP_ERR_INVALID_ARG, "recon must be 18 or 12");
+        if (U->recon != 18 && U->recon != 12 && U->recon != 8)
+            return sp::set_error(SP_ERR_INVALID_ARG, "recon must be 18, 12 or 8");
+        if (U->recon == 8 && U->lo_prec != SP_F32)
+            return sp::set_error(SP_ERR_UNSUPPORTED, "recon 8 is built for FP32 links only");
         links = U->lo;
         lp = U->lo_prec;
         recon = U->recon;

@@ -19,8 +19,8 @@ from gpu_common import DEV, DSLASH_TOL, announce, to_dev, to_host
 pytestmark = pytest.mark.gpu
 
 # (vector precision, link precision, recon)
-PACKINGS = [("f64", "f64", 18), ("f32", "f32", 12), ("f32", "f32", 18), ("f16", "f16", 12), ("bf16", "bf16", 18),
-            ("f32", "f16", 12), ("f32", "i16", 12)]
+PACKINGS = [("f64", "f64", 18), ("f32", "f32", 12), ("f32", "f32", 18), ("f32", "f32", 8), ("f16", "f16", 12),
+            ("bf16", "bf16", 18), ("f32", "f16", 12), ("f32", "i16", 12)]
 
 
 def _tol(vp, lp):
