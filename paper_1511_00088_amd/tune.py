@@ -1,7 +1,10 @@
 """Tune the half-Dslash launch (block size, XCD-aware block order, link-load policy) for a set of lattice shapes
 and storage precisions on the current GPU and write the table that sp_tune_load reads.
 
-    python -m paper_1511_00088_amd.tune OUT.json [--dims X Y Z T ...]
+    python -m paper_1511_00088_amd.tune OUT.json [--dims X Y Z T ...] [--recon R ...] [--base TABLE.json]
+
+--recon keeps the combinations of those link packings only; --base loads an existing table first, so that
+OUT.json holds its entries with the newly tuned ones replacing or joining them.
 """
 from __future__ import annotations
 
@@ -16,7 +19,8 @@ from . import api
 DEFAULT_DIMS = [(20, 20, 20, 64), (8, 8, 8, 8), (12, 12, 12, 24), (16, 16, 16, 32), (32, 32, 32, 64),
                 (28, 28, 28, 96), (20, 20, 20, 8)]
 # (vector precision, recon, link precision): each storage precision alone, and 16-bit links with FP32 vectors
-COMBOS = [("f64", 18, "f64"), ("f32", 18, "f32"), ("f32", 12, "f32"), ("f16", 18, "f16"), ("f16", 12, "f16"),
+COMBOS = [("f64", 18, "f64"), ("f32", 18, "f32"), ("f32", 12, "f32"), ("f32", 8, "f32"), ("f16", 18, "f16"),
+          ("f16", 12, "f16"),
           ("bf16", 18, "bf16"), ("bf16", 12, "bf16"), ("f32", 12, "f16"), ("f32", 18, "f16"), ("f32", 12, "bf16"),
           ("f32", 18, "bf16"), ("f32", 12, "i16"), ("f32", 18, "i16")]
 
@@ -25,23 +29,31 @@ def tune_all(dims_list, combos=COMBOS, device="cuda:0"):
     out = []
     for dims in dims_list:
         lat = api.Lattice(dims)
-        # the launch shape does not depend on the link values: identity links suffice
+        # the launch shape does not depend on the link values: identity links suffice, and for recon 8 (which
+        # cannot store a first row (1, 0, 0)) a rotation by pi/4 in the (0, 1) plane
         links = torch.zeros((4, lat.V, 3, 3), dtype=torch.complex128, device=device)
         links[..., 0, 0] = links[..., 1, 1] = links[..., 2, 2] = 1.0
+        rot = None
         for prec, recon, lp in combos:
-            g = api.Gauge(lat, links, lo_prec=lp, recon=recon)
+            if recon == 8 and rot is None:
+                c = 0.5 ** 0.5
+                rot = torch.zeros_like(links)
+                rot[..., 0, 0] = rot[..., 1, 1] = rot[..., 0, 1] = c
+                rot[..., 1, 0] = -c
+                rot[..., 2, 2] = 1.0
+            g = api.Gauge(lat, rot if recon == 8 else links, lo_prec=lp, recon=recon)
             ms = api.tune_dslash(g, prec)
             out.append((dims, prec, recon, lp, ms))
             print(f"{dims} {prec} r{recon} links {lp}: {ms * 1e3:.2f} us", flush=True)
             del g
-        del links
+        del links, rot
     return out
 
 
 PREC_CODE = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3, "i16": 4}
 # single-solve combinations whose iteration is tuned on the solver's own launches: (inner, recon, link precision)
-SOLVE_COMBOS = [("f32", 12, "f32"), ("f32", 18, "f32"), ("f64", 18, "f64"), ("f32", 12, "i16"), ("f32", 12, "f16"),
-                ("f16", 12, "f16"), ("bf16", 12, "bf16")]
+SOLVE_COMBOS = [("f32", 12, "f32"), ("f32", 18, "f32"), ("f32", 8, "f32"), ("f64", 18, "f64"), ("f32", 12, "i16"),
+                ("f32", 12, "f16"), ("f16", 12, "f16"), ("bf16", 12, "bf16")]
 
 
 def _table(entries):
@@ -128,14 +140,19 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("out")
     ap.add_argument("--dims", type=int, nargs="+", default=None, help="groups of 4 extents")
+    ap.add_argument("--recon", type=int, nargs="+", default=None, help="tune only these link packings")
+    ap.add_argument("--base", default=None, help="a table to load first and keep the other entries of")
     a = ap.parse_args()
     dims_list = DEFAULT_DIMS
     if a.dims:
         if len(a.dims) % 4:
             raise SystemExit("--dims takes groups of 4 extents")
         dims_list = [tuple(a.dims[i:i + 4]) for i in range(0, len(a.dims), 4)]
-    tune_all(dims_list)
-    tune_solves([d for d in dims_list if d[0] * d[1] * d[2] * d[3] >= 4096])
+    if a.base:
+        api.tune_load(a.base)
+    keep = (lambda c: c[1] in a.recon) if a.recon else (lambda c: True)
+    tune_all(dims_list, [c for c in COMBOS if keep(c)])
+    tune_solves([d for d in dims_list if d[0] * d[1] * d[2] * d[3] >= 4096], [c for c in SOLVE_COMBOS if keep(c)])
     api.tune_save(a.out)
 
 

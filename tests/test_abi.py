@@ -172,7 +172,8 @@ def test_shipped_tune_table_loads_and_covers_the_workloads():
         table = json.load(f)
     for key in ("20x20x20x64/l1/r12/v1", "20x20x20x64/l1/r12/v1/n4", "20x20x20x64/l1/r12/v1/solve",
                 "20x20x20x64/l4/r12/v1/solve", "20x20x20x64/l0/r18/v0/solve", "32x32x32x64/l1/r12/v1/solve",
-                "28x28x28x96/l1/r12/v1/solve"):
+                "28x28x28x96/l1/r12/v1/solve", "20x20x20x64/l1/r8/v1", "20x20x20x64/l1/r8/v1/solve",
+                "32x32x32x64/l1/r8/v1/solve"):
         assert key in table, key
         assert table[key]["nt"] in (64, 128, 256) and table[key]["remap"] in (0, 1)
         assert table[key].get("stream", 0) in (0, 1)
